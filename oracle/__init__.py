@@ -1,0 +1,27 @@
+"""FP64 CPU oracle for the whitening + 1D-ResNet scoring path (test infrastructure).
+
+This package is a plain, slow, obviously correct NumPy implementation of what
+the GPU library computes, written from the paper's description of the method
+(Welch PSD, inverse-ASD whitening filter with 0.5 s settle-in per edge,
+windowed residual-CNN scoring, 1 s top-hat integration).  It exists only to
+check the GPU path: it is imported by the test-suite, by the smoke check and by
+the benchmark's CPU-baseline leg, never by the library itself.  It shares no
+code with the HIP path; the only common module is `synth`, which generates the
+seeded inputs and holds none of the method's arithmetic.
+
+Parity status: every function here is pinned by tests/test_oracle_*.py against
+closed forms, brute-force sums, library routines or invariants; see each
+module's header.
+"""
+from .welch import hann_periodic, welch_psd, welch_psd_rolling, periodogram_dft
+from .whiten import whitening_fir, whiten, whiten_piecewise, whiten_at
+from .net import fold_bn, conv1d, net_forward, net_forward_quant
+from .post import integrate, kendall_tau_b, unfold_windows
+from .quant import bf16_round, e4m3_round
+
+__all__ = [
+    "hann_periodic", "welch_psd", "welch_psd_rolling", "periodogram_dft",
+    "whitening_fir", "whiten", "whiten_piecewise", "whiten_at",
+    "fold_bn", "conv1d", "net_forward", "net_forward_quant",
+    "integrate", "kendall_tau_b", "unfold_windows", "bf16_round", "e4m3_round",
+]
