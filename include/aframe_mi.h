@@ -1,0 +1,173 @@
+/*
+ * aframe_mi.h — C ABI of the MI355X (gfx950) whitening + 1D-ResNet scoring library.
+ *
+ * The library implements the data-parallel hot path of a machine-learning
+ * search for compact-binary-coalescence gravitational waves (Aframe,
+ * arXiv:2403.18661): estimate each detector's noise PSD (Sec. IV.B noise
+ * sampling, Sec. VI), build an inverse-ASD whitening filter and whiten the
+ * strain, cropping the filter's 0.5 s settle-in at each edge (Sec. IV.B,
+ * Table III), score overlapping 1.5 s two-detector windows with a 1D residual
+ * CNN that returns one scalar detection statistic per window (Sec. II), and
+ * smooth the statistic with a 1 s top hat (Sec. II).
+ *
+ * Conventions shared by every entry point
+ *  - All data pointers are DEVICE pointers on the current HIP device unless a
+ *    parameter says "host".  The caller owns every buffer (inputs, outputs and
+ *    workspace); the library owns only af_net objects and its internal
+ *    constant tables (FFT twiddles, windows), created on first use per device.
+ *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
+ *    Only af_net_create synchronises (it uploads the weights).
+ *  - Every argument is validated on the host before anything is launched; an
+ *    invalid call returns AF_EINVAL and leaves outputs untouched.  HIP runtime
+ *    failures return AF_EHIP.  af_last_error() returns a message for the last
+ *    failing call on the calling thread.
+ *  - Calls on distinct streams and distinct workspaces may run concurrently;
+ *    one af_net may be used from several streams at once (it is read-only).
+ */
+#ifndef AFRAME_MI_H
+#define AFRAME_MI_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    AF_OK = 0,
+    AF_EINVAL = -1,        /* bad argument or shape; nothing launched            */
+    AF_ENOMEM = -2,        /* host or device allocation failed                  */
+    AF_EHIP = -3,          /* HIP runtime error (message in af_last_error)      */
+    AF_EUNSUPPORTED = -4   /* valid request that this build does not implement  */
+} af_status;
+
+typedef void* af_stream;   /* hipStream_t */
+
+typedef enum { AF_IN_F64 = 0, AF_IN_F32 = 1 } af_dtype;
+typedef enum { AF_F32 = 0, AF_BF16 = 1, AF_FP8 = 2 } af_precision;
+
+/* Message describing the last error on this thread ("" if none). */
+const char* af_last_error(void);
+/* Library version string. */
+const char* af_version(void);
+
+/* ------------------------------------------------------------------------
+ * Welch PSD (Sec. IV.B noise sampling; Sec. VI: "the first 64 seconds ... to
+ * estimate the PSD").  One-sided PSD with periodic-Hann segments of `nperseg`
+ * samples every nperseg - noverlap samples, mean of |rFFT|^2 over segments,
+ * density scaling c_k / (fs sum w^2) with c_0 = c_{nperseg/2} = 1, else 2.
+ *
+ * x      : [n_ch][ld_x] strain (AF_IN_F64: physical strain, AF_IN_F32: any
+ *          float series); every sample is multiplied by `prescale` on load
+ *          (1e21 brings physical strain to O(1)).
+ * PSD j (j < n_psd) is estimated from x[:, j*psd_hop : j*psd_hop + psd_len]
+ * (a rolling background); psd_hop must be a multiple of nperseg - noverlap
+ * when n_psd > 1.  With n_psd = 1, psd_hop is ignored.
+ * psd    : [n_psd][n_ch][nperseg/2 + 1] float64 output, in (prescale*x)^2/Hz.
+ * nperseg: power of two in [256, 4096].
+ * Segment spectra and averaging are computed in FP64.
+ * ws     : device workspace of at least af_psd_workspace_bytes(...) bytes.
+ * ------------------------------------------------------------------------ */
+size_t af_psd_workspace_bytes(int64_t n_ch, int64_t nperseg, int64_t noverlap,
+                              int64_t psd_len, int64_t psd_hop, int64_t n_psd);
+af_status af_psd_estimate(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x,
+                          double fs, double prescale, int64_t nperseg, int64_t noverlap,
+                          int64_t psd_len, int64_t psd_hop, int64_t n_psd,
+                          double* psd, void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Whitening (Sec. IV.B: PSD -> whitening filter -> whiten in the frequency
+ * domain -> crop 0.5 s per edge; Sec. VI; Table III "cropping corruption
+ * from whitening filter").  The filter is the inverse ASD with bins below
+ * `highpass` zeroed, transformed to a zero-phase impulse response and
+ * truncated with a Hann taper to |m| < M = fduration*fs/2 taps per side:
+ *     y[c][i] = sqrt(2/fs) * sum_m h_j[c][m] * prescale * x[c][out_start + i - m]
+ * for i < n_out, with j = min(i / psd_hop, n_psd - 1).  In-band white output
+ * has unit variance.  The filter is built in FP64 on the device; the
+ * convolution runs as FP32 overlap-save FFTs of 8192 points.
+ *
+ * psd    : [n_psd][n_ch][nperseg/2+1] float64 (as written by af_psd_estimate
+ *          with the same prescale).  nperseg in {2048, 4096}, 2M-1 <= nperseg.
+ * Context: out_start >= M and out_start + n_out + M <= n.
+ * y      : [n_ch][ld_y] float32 output, ld_y >= n_out.
+ * ------------------------------------------------------------------------ */
+size_t af_whiten_workspace_bytes(int64_t n_ch, int64_t nperseg, int64_t n_psd);
+af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x,
+                    double fs, double prescale, const double* psd, int64_t nperseg,
+                    int64_t n_psd, int64_t psd_hop, double fduration, double highpass,
+                    int64_t out_start, int64_t n_out, float* y, int64_t ld_y,
+                    void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Scoring network (Sec. II: 1D-convolutional ResNet mapping a two-detector
+ * window to one scalar detection statistic).  Architecture: stem conv (kernel
+ * k, stride stem_stride) + BN + ReLU [+ max-pool 3/2/1]; n_stages stages of
+ * BasicBlocks (conv-BN-ReLU-conv-BN + skip, ReLU), stride 2 at the first block
+ * of stages > 0, 1x1 conv + BN projection where the shape changes; global
+ * average pool; FC -> 1 logit.  BatchNorm is folded into the convs
+ * (eval mode, eps 1e-5) when the net is created.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t in_ch;        /* detectors (2)                       */
+    int32_t stem_ch;      /* stem output channels                */
+    int32_t kernel;       /* conv kernel size (odd)              */
+    int32_t stem_stride;  /* 1 or 2                              */
+    int32_t stem_pool;    /* 1: max-pool k3 s2 p1 after the stem */
+    int32_t n_stages;     /* <= 8                                */
+    int32_t widths[8];
+    int32_t blocks[8];
+    int32_t window;       /* samples per window (3072 = 1.5 s)   */
+} af_net_desc;
+
+typedef struct af_net af_net;
+
+/* params (host, float64): for each conv in execution order (stem; then per
+ * block conv1, conv2, [proj]) its weight [C_out][C_in][k] followed by its BN
+ * gamma, beta, running_mean, running_var [C_out]; then fc weight [C_last] and
+ * fc bias [1].  n_params must equal the total.  Weights are folded in FP64 and
+ * stored in `precision` (FP8: E4M3 with per-output-channel scales max|W'|/448).
+ * Synchronous.  *out receives the handle. */
+af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n_params,
+                        af_precision precision, af_net** out);
+void af_net_destroy(af_net* net);
+/* Total conv + FC multiply-accumulates per window. */
+int64_t af_net_macs(const af_net* net);
+
+/* Number of timed layers: stem, each conv in execution order, GAP+FC head. */
+int64_t af_net_n_layers(const af_net* net);
+/* Kernel timing (a tracing aid, Sec. VIII reports per-stage latencies).
+ * Between begin and end, every af_score_windows call on this net records a HIP
+ * event pair around each kernel it launches (on the call's stream).  end()
+ * waits for those events and writes, per layer index (0 = stem, 1.. = convs
+ * in execution order, last = head): total milliseconds, launch count and
+ * algorithmic FLOPs (2 x MACs x windows).  Arrays have af_net_n_layers()
+ * entries.  Not thread-safe with concurrent scoring on the same net. */
+af_status af_net_profile_begin(af_net* net);
+af_status af_net_profile_end(af_net* net, int64_t n_layers, double* ms, int64_t* launches, double* flops);
+
+/* Workspace needed to score `batch` windows per internal pass. */
+size_t af_score_workspace_bytes(const af_net* net, int64_t batch);
+/* logits[i] = net(window i) for i < n_windows.  Channel c of window i is
+ *   y[c*ld_y + p], p = i*stride + ch_shift[c] + t, t < window,
+ * with p taken modulo `wrap` when wrap > 0 (circular timeslides, Sec. IX).
+ * ch_shift: host array [n_ch] or NULL (all 0).  Without wrap every p must be
+ * < n.  y is float32; it is rounded to the net's precision inside the kernels.
+ * Windows are processed in passes of the largest batch the workspace holds. */
+af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y,
+                           int64_t n, int64_t stride, int64_t n_windows,
+                           const int64_t* ch_shift, int64_t wrap, float* logits,
+                           void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Integration (Sec. II: predictions integrated with a 1 s top-hat filter).
+ * Causal right-aligned mean, valid mode:
+ *     out[i] = (1/width) sum_{j=i}^{i+width-1} p[j],  i < n - width + 1.
+ * n < width writes nothing.
+ * ------------------------------------------------------------------------ */
+af_status af_integrate(const float* p, int64_t n, int64_t width, float* out, af_stream stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* AFRAME_MI_H */

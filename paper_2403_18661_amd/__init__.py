@@ -1,0 +1,199 @@
+"""MI355X-native whitening + 1D-ResNet scoring for two-detector strain.
+
+Thin Python binding over libaframe_mi.so (C ABI: include/aframe_mi.h).  Each
+function marshals torch tensors (device memory) and the current HIP stream into
+one C call; every step of the computation runs in the library's HIP kernels.
+The functions follow the paper's pipeline (arXiv:2403.18661): Welch PSD of a
+background stretch, whitening with an inverse-ASD FIR that loses 0.5 s per
+edge, per-window scoring by a residual 1D CNN, 1 s top-hat integration.
+"""
+import ctypes
+
+import numpy as np
+import torch
+
+from ._lib import AframeError, NetDesc, check, lib
+
+__all__ = ["psd_estimate", "whiten", "Net", "integrate", "pack_params", "AframeError", "lib"]
+
+AF_IN_F64, AF_IN_F32 = 0, 1
+PRECISIONS = {"f32": 0, "bf16": 1, "fp8": 2}
+
+
+def _stream(stream):
+    s = torch.cuda.current_stream() if stream is None else stream
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr()) if t is not None else ctypes.c_void_p(0)
+
+
+def _check_dev(t, name, dtypes):
+    if not (isinstance(t, torch.Tensor) and t.is_cuda):
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if t.dtype not in dtypes:
+        raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
+    if t.stride(-1) != 1:
+        raise ValueError(f"{name} must be contiguous in its last dimension")
+
+
+def _in_dtype(x):
+    return AF_IN_F64 if x.dtype == torch.float64 else AF_IN_F32
+
+
+def _workspace(nbytes, device):
+    return torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+
+
+def psd_estimate(x, fs, prescale=1.0, nperseg=4096, noverlap=None, psd_len=None, psd_hop=0, n_psd=1,
+                 out=None, ws=None, stream=None):
+    """Welch PSD of x [n_ch, n] -> [n_psd, n_ch, nperseg//2+1] float64 (af_psd_estimate)."""
+    _check_dev(x, "x", (torch.float64, torch.float32))
+    n_ch, n = x.shape
+    noverlap = nperseg // 2 if noverlap is None else noverlap
+    psd_len = n if psd_len is None else psd_len
+    F = nperseg // 2 + 1
+    if out is None:
+        out = torch.empty((n_psd, n_ch, F), dtype=torch.float64, device=x.device)
+    need = lib().af_psd_workspace_bytes(n_ch, nperseg, noverlap, psd_len, psd_hop, n_psd)
+    ws = _workspace(need, x.device) if ws is None else ws
+    check(lib().af_psd_estimate(_ptr(x), _in_dtype(x), n_ch, n, x.stride(0), fs, prescale, nperseg, noverlap,
+                                psd_len, psd_hop, n_psd, _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def whiten(x, psd, fs, prescale=1.0, psd_hop=0, fduration=1.0, highpass=32.0, out_start=None, n_out=None,
+           out=None, ws=None, stream=None):
+    """Whiten x [n_ch, n] with psd [n_psd, n_ch, F] -> y [n_ch, n_out] float32 (af_whiten).
+    Default output range: crop fduration/2 at each edge."""
+    _check_dev(x, "x", (torch.float64, torch.float32))
+    _check_dev(psd, "psd", (torch.float64,))
+    if psd.dim() == 2:
+        psd = psd.unsqueeze(0)
+    n_psd, _, F = psd.shape
+    nperseg = 2 * (F - 1)
+    n_ch, n = x.shape
+    M = int(round(fduration * fs / 2))
+    out_start = M if out_start is None else out_start
+    n_out = n - out_start - M if n_out is None else n_out
+    if out is None:
+        out = torch.empty((n_ch, n_out), dtype=torch.float32, device=x.device)
+    need = lib().af_whiten_workspace_bytes(n_ch, nperseg, n_psd)
+    ws = _workspace(need, x.device) if ws is None else ws
+    check(lib().af_whiten(_ptr(x), _in_dtype(x), n_ch, n, x.stride(0), fs, prescale, _ptr(psd.contiguous()),
+                          nperseg, n_psd, psd_hop, fduration, highpass, out_start, n_out, _ptr(out),
+                          out.stride(0), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
+
+
+def pack_params(params, arch):
+    """Flatten a name -> array parameter dict into the C ABI's order: per conv
+    (stem; per block conv1, conv2, [proj]) weight then BN gamma, beta, mean,
+    var; then FC weight and bias.  `arch` provides block_list()."""
+    parts = []
+
+    def conv(c, bn):
+        parts.append(np.asarray(params[c + ".w"], np.float64).ravel())
+        for k in ("gamma", "beta", "mean", "var"):
+            parts.append(np.asarray(params[f"{bn}.{k}"], np.float64).ravel())
+
+    conv("stem.conv", "stem.bn")
+    for pre, _, _, _, proj in arch.block_list():
+        conv(pre + ".conv1", pre + ".bn1")
+        conv(pre + ".conv2", pre + ".bn2")
+        if proj:
+            conv(pre + ".proj", pre + ".projbn")
+    parts.append(np.asarray(params["fc.w"], np.float64).ravel())
+    parts.append(np.asarray(params["fc.b"], np.float64).ravel())
+    return np.ascontiguousarray(np.concatenate(parts))
+
+
+class Net:
+    """A scoring network resident on the current device (af_net_create)."""
+
+    def __init__(self, arch, params, precision="f32"):
+        d = NetDesc()
+        d.in_ch, d.stem_ch, d.kernel = arch.in_ch, arch.stem_ch, arch.kernel
+        d.stem_stride, d.stem_pool, d.n_stages = arch.stem_stride, int(arch.stem_pool), len(arch.widths)
+        for i, (w, b) in enumerate(zip(arch.widths, arch.blocks)):
+            d.widths[i], d.blocks[i] = w, b
+        d.window = arch.window
+        flat = params if isinstance(params, np.ndarray) else pack_params(params, arch)
+        flat = np.ascontiguousarray(flat, dtype=np.float64)
+        self.window = arch.window
+        self.in_ch = arch.in_ch
+        self.precision = precision
+        h = ctypes.c_void_p()
+        check(lib().af_net_create(ctypes.byref(d), flat.ctypes.data_as(ctypes.c_void_p), flat.size,
+                                  PRECISIONS[precision], ctypes.byref(h)))
+        self._h = h
+
+    def close(self):
+        """Free the device weights now (also done when the object is collected)."""
+        h = getattr(self, "_h", None)
+        if h is not None and h.value:
+            lib().af_net_destroy(h)
+        self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:   # interpreter shutdown: the library may already be unloaded
+            pass
+
+    @property
+    def macs(self):
+        return lib().af_net_macs(self._h)
+
+    @property
+    def n_layers(self):
+        return lib().af_net_n_layers(self._h)
+
+    def profile_begin(self):
+        """Start per-kernel HIP-event timing of score_windows calls."""
+        check(lib().af_net_profile_begin(self._h))
+
+    def profile_end(self):
+        """Stop timing; return per-layer dict arrays ms, launches, flops
+        (layer 0 = stem, then convs in execution order, last = head)."""
+        n = self.n_layers
+        ms = np.zeros(n)
+        la = np.zeros(n, dtype=np.int64)
+        fl = np.zeros(n)
+        check(lib().af_net_profile_end(self._h, n, ms.ctypes.data_as(ctypes.c_void_p),
+                                       la.ctypes.data_as(ctypes.c_void_p), fl.ctypes.data_as(ctypes.c_void_p)))
+        return {"ms": ms, "launches": la, "flops": fl}
+
+    def workspace_bytes(self, batch):
+        return lib().af_score_workspace_bytes(self._h, batch)
+
+    def score_windows(self, y, stride, n_windows=None, shifts=None, wrap=0, batch=1024, out=None, ws=None,
+                      stream=None):
+        """Logits of windows of y [n_ch, n] float32 (af_score_windows)."""
+        _check_dev(y, "y", (torch.float32,))
+        n_ch, n = y.shape
+        if n_windows is None:
+            n_windows = 0 if n < self.window else (n - self.window) // stride + 1
+        if out is None:
+            out = torch.empty(n_windows, dtype=torch.float32, device=y.device)
+        if ws is None:
+            ws = _workspace(self.workspace_bytes(max(1, min(batch, n_windows))), y.device)
+        sh = None
+        if shifts is not None:
+            sh = (ctypes.c_int64 * n_ch)(*[int(v) for v in shifts])
+        check(lib().af_score_windows(self._h, _ptr(y), n_ch, y.stride(0), n, stride, n_windows,
+                                     ctypes.cast(sh, ctypes.c_void_p) if sh is not None else None, wrap,
+                                     _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+        return out
+
+
+def integrate(p, width, out=None, stream=None):
+    """Causal 1 s top-hat mean of logits p [n] -> [n - width + 1] (af_integrate)."""
+    _check_dev(p, "p", (torch.float32,))
+    n = p.numel()
+    m = max(n - width + 1, 0)
+    if out is None:
+        out = torch.empty(m, dtype=torch.float32, device=p.device)
+    check(lib().af_integrate(_ptr(p), n, width, _ptr(out), _stream(stream)))
+    return out

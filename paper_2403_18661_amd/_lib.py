@@ -1,0 +1,71 @@
+"""ctypes declarations of libaframe_mi.so (the C ABI in include/aframe_mi.h)."""
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libaframe_mi.so")
+
+c_i64 = ctypes.c_int64
+c_dbl = ctypes.c_double
+c_vp = ctypes.c_void_p
+c_sz = ctypes.c_size_t
+c_int = ctypes.c_int
+
+
+class NetDesc(ctypes.Structure):
+    _fields_ = [("in_ch", ctypes.c_int32), ("stem_ch", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("stem_stride", ctypes.c_int32), ("stem_pool", ctypes.c_int32), ("n_stages", ctypes.c_int32),
+                ("widths", ctypes.c_int32 * 8), ("blocks", ctypes.c_int32 * 8), ("window", ctypes.c_int32)]
+
+
+# name -> (restype, argtypes); the list is also the set of exported symbols
+SIGNATURES = {
+    "af_last_error": (ctypes.c_char_p, []),
+    "af_version": (ctypes.c_char_p, []),
+    "af_psd_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_i64, c_i64]),
+    "af_psd_estimate": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_i64, c_i64, c_i64, c_i64,
+                                c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "af_whiten_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
+    "af_whiten": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_vp, c_i64, c_i64, c_i64, c_dbl,
+                          c_dbl, c_i64, c_i64, c_vp, c_i64, c_vp, c_sz, c_vp]),
+    "af_net_create": (c_int, [ctypes.POINTER(NetDesc), c_vp, c_i64, c_int, ctypes.POINTER(c_vp)]),
+    "af_net_destroy": (None, [c_vp]),
+    "af_net_macs": (c_i64, [c_vp]),
+    "af_score_workspace_bytes": (c_sz, [c_vp, c_i64]),
+    "af_net_n_layers": (c_i64, [c_vp]),
+    "af_net_profile_begin": (c_int, [c_vp]),
+    "af_net_profile_end": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "af_score_windows": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp,
+                                 c_sz, c_vp]),
+    "af_integrate": (c_int, [c_vp, c_i64, c_i64, c_vp, c_vp]),
+}
+
+_lib = None
+
+
+def lib():
+    """Load the library (once).  Raises ImportError if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2403_18661_amd.build`")
+        L = ctypes.CDLL(LIB_PATH)
+        for name, (res, args) in SIGNATURES.items():
+            fn = getattr(L, name)
+            fn.restype = res
+            fn.argtypes = args
+        _lib = L
+    return _lib
+
+
+class AframeError(RuntimeError):
+    pass
+
+
+STATUS = {0: "AF_OK", -1: "AF_EINVAL", -2: "AF_ENOMEM", -3: "AF_EHIP", -4: "AF_EUNSUPPORTED"}
+
+
+def check(status):
+    if status != 0:
+        msg = lib().af_last_error().decode()
+        raise AframeError(f"{STATUS.get(status, status)}: {msg}")

@@ -1,0 +1,460 @@
+// Scoring network: creation (BatchNorm folding, precision conversion, device
+// layouts), execution plan and the af_score_windows entry point.
+#include <cfenv>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "net_kernels.h"
+
+using namespace afm;
+
+namespace {
+
+using LaunchFn = void (*)(const ConvArgs&, int, hipStream_t);
+
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC>
+void launch_conv(const ConvArgs& a0, int n_win, hipStream_t s) {
+    constexpr int MT = WM * TM * 16, NT = WN * TN * 16;
+    ConvArgs a = a0;
+    a.tiles_per_win = (a.L_out + MT - 1) / MT;
+    dim3 grid((unsigned)(n_win * a.tiles_per_win), (unsigned)(a.C_out / NT));
+    hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC>), grid, dim3(64 * WM * WN), 0, s, a);
+}
+
+// Tile shape by output width: 16 -> 256x16, 32 -> 192x32, 64 -> 96x64, >=128 -> 96x128.
+template <typename P, int KW, int S, int KC>
+LaunchFn pick_by_width(int c_out) {
+    if (c_out == 16) return launch_conv<P, KW, S, 4, 1, 4, 1, KC>;
+    if (c_out == 32) return launch_conv<P, KW, S, 4, 1, 3, 2, KC>;
+    if (c_out == 64) return launch_conv<P, KW, S, 2, 2, 3, 2, KC>;
+    if (c_out % 128 == 0) return launch_conv<P, KW, S, 2, 2, 3, 4, KC>;
+    return nullptr;
+}
+
+template <typename P, int KC>
+LaunchFn pick_shape(int kw, int s, int c_out) {
+    if (kw == 7 && s == 1) return pick_by_width<P, 7, 1, KC>(c_out);
+    if (kw == 7 && s == 2) return c_out >= 64 ? pick_by_width<P, 7, 2, KC>(c_out) : nullptr;
+    if (kw == 1 && s == 2) return c_out >= 64 ? pick_by_width<P, 1, 2, KC>(c_out) : nullptr;
+    return nullptr;
+}
+
+LaunchFn pick_conv(af_precision p, int kw, int s, int c_in, int c_out) {
+    if (p == AF_F32) return c_in % 16 == 0 ? pick_shape<PF32, 16>(kw, s, c_out) : nullptr;
+    const bool kc32 = c_in % 32 == 0;
+    if (kw == 1 && !kc32) return nullptr;  // a 1x1 chunk must fill a whole 32-deep MFMA
+    if (p == AF_BF16)
+        return kc32 ? pick_shape<PBF16, 32>(kw, s, c_out) : (c_in % 16 == 0 ? pick_shape<PBF16, 16>(kw, s, c_out) : nullptr);
+    return kc32 ? pick_shape<PFP8, 32>(kw, s, c_out) : (c_in % 16 == 0 ? pick_shape<PFP8, 16>(kw, s, c_out) : nullptr);
+}
+
+// ---- host rounding onto BF16 / E4M3 grids (round to nearest even) -----------------
+double round_sig(double x, int sig, int min_exp, int step_exp) {
+    if (x == 0.0) return 0.0;
+    if (std::fabs(x) < std::ldexp(1.0, min_exp)) return std::ldexp(std::nearbyint(std::ldexp(x, -step_exp)), step_exp);
+    int e;
+    double m = std::frexp(x, &e);
+    return std::ldexp(std::nearbyint(std::ldexp(m, sig)), e - sig);
+}
+uint16_t host_bf16_bits(double v) {
+    float f = (float)round_sig(v, 8, -126, -133);  // exact: the value is on the BF16 grid
+    uint32_t u;
+    std::memcpy(&u, &f, 4);
+    return (uint16_t)(u >> 16);
+}
+uint8_t host_e4m3_bits(double v) {
+    double r = round_sig(v, 4, -6, -9);
+    if (r > 448.0) r = 448.0;
+    if (r < -448.0) r = -448.0;
+    uint8_t sign = r < 0 ? 0x80 : 0;
+    double a = std::fabs(r);
+    if (a == 0.0) return sign;
+    if (a < 0.015625) return sign | (uint8_t)std::lrint(a * 512.0);
+    int e;
+    double m = std::frexp(a, &e);           // a = m 2^e, m in [0.5, 1)
+    int E = e - 1;                          // a = (2m) 2^E, 2m in [1, 2)
+    int mant = (int)std::lrint((2.0 * m - 1.0) * 8.0);
+    return sign | (uint8_t)(((E + 7) << 3) | mant);
+}
+
+enum Buf { BX = 0, BR = 1, BP = 2 };
+
+struct ConvOp {
+    int c_in, c_out, kw, s, l_in, l_out, relu;
+    int in_buf, out_buf, res_buf;  // res_buf < 0: none
+    int amax_in, amax_out;         // FP8 slots
+    size_t w_off, b_off;
+    LaunchFn fn;
+};
+
+}  // namespace
+
+struct af_net {
+    af_net_desc desc;
+    af_precision prec;
+    int device;
+    int64_t macs;
+    int stem_lconv, stem_lout;
+    int64_t act_elems;  // per window, max over layers
+    int n_slots;
+    int last_L, last_C;
+    float fc_b;
+    std::vector<ConvOp> ops;
+    void* d_w = nullptr;       // conv weights in storage type
+    float* d_b = nullptr;      // conv biases
+    float* d_ws = nullptr;     // FP8 per-output-channel scales
+    float* d_stem = nullptr;   // stem weights [C][in][k] then bias [C]
+    float* d_fc = nullptr;     // fc weights [C_last]
+    // kernel timing (af_net_profile_begin/end): one event pair per launch
+    bool profiling = false;
+    struct Rec {
+        int layer;
+        int64_t windows;
+        hipEvent_t a, b;
+    };
+    std::vector<Rec> recs;
+    std::vector<int64_t> layer_macs;  // per window: stem, convs..., gap/fc
+};
+
+namespace {
+size_t act_size(af_precision p) { return p == AF_F32 ? 4 : 2; }
+
+void drop_records(af_net* n) {
+    for (auto& r : n->recs) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    n->recs.clear();
+}
+
+void free_net(af_net* n) {
+    if (!n) return;
+    drop_records(n);
+    if (n->d_w) (void)hipFree(n->d_w);
+    if (n->d_b) (void)hipFree(n->d_b);
+    if (n->d_ws) (void)hipFree(n->d_ws);
+    if (n->d_stem) (void)hipFree(n->d_stem);
+    if (n->d_fc) (void)hipFree(n->d_fc);
+    delete n;
+}
+}  // namespace
+
+extern "C" af_status af_net_create(const af_net_desc* d, const double* params, int64_t n_params,
+                                   af_precision prec, af_net** out) {
+    clear_error();
+    AF_CHECK_ARG(d && params && out, "desc, params and out must be non-null");
+    AF_CHECK_ARG(prec == AF_F32 || prec == AF_BF16 || prec == AF_FP8, "unknown precision %d", (int)prec);
+    AF_CHECK_ARG(d->in_ch >= 1 && d->in_ch <= 4, "in_ch must be in [1, 4]");
+    AF_CHECK_ARG(d->kernel == 7, "only kernel 7 is implemented");
+    AF_CHECK_ARG(d->stem_stride == 1 || d->stem_stride == 2, "stem_stride must be 1 or 2");
+    AF_CHECK_ARG(d->n_stages >= 1 && d->n_stages <= 8, "n_stages must be in [1, 8]");
+    AF_CHECK_ARG(d->window >= 16 && d->window <= 16384, "window must be in [16, 16384]");
+    AF_CHECK_ARG(d->stem_ch >= 16 && 256 % d->stem_ch == 0, "stem_ch must divide 256 and be >= 16");
+    const int K = d->kernel;
+    af_net* net = new (std::nothrow) af_net();
+    if (!net) { set_error("out of host memory"); return AF_ENOMEM; }
+    net->desc = *d;
+    net->prec = prec;
+    (void)hipGetDevice(&net->device);
+
+    // ---- walk the architecture, fold BN, build the op list --------------------
+    const double* p = params;
+    const double* p_end = params + n_params;
+    std::vector<float> stem;       // weights then bias
+    std::vector<double> wfold;     // all MFMA conv weights, [C_out][KW][C_in], folded
+    std::vector<float> bias;
+    auto take_conv = [&](int c_out, int c_in, int kw, std::vector<double>& w, std::vector<double>& b) -> bool {
+        const size_t nw = (size_t)c_out * c_in * kw;
+        if (p + nw + 4 * (size_t)c_out > p_end) return false;
+        const double* W = p;
+        const double *g = W + nw, *be = g + c_out, *mu = be + c_out, *var = mu + c_out;
+        w.assign(nw, 0.0);
+        b.assign(c_out, 0.0);
+        for (int o = 0; o < c_out; ++o) {
+            const double s = g[o] / std::sqrt(var[o] + 1e-5);
+            b[o] = be[o] - mu[o] * s;
+            for (int c = 0; c < c_in; ++c)
+                for (int j = 0; j < kw; ++j)  // reorder to [o][j][c]
+                    w[((size_t)o * kw + j) * c_in + c] = W[((size_t)o * c_in + c) * kw + j] * s;
+        }
+        p = var + c_out;
+        return true;
+    };
+    std::vector<double> w, b;
+    if (!take_conv(d->stem_ch, d->in_ch, K, w, b)) { free_net(net); set_error("params too short"); return AF_EINVAL; }
+    stem.resize((size_t)d->stem_ch * d->in_ch * K + d->stem_ch);
+    for (int o = 0; o < d->stem_ch; ++o)
+        for (int c = 0; c < d->in_ch; ++c)
+            for (int j = 0; j < K; ++j)
+                stem[((size_t)o * d->in_ch + c) * K + j] = (float)w[((size_t)o * K + j) * d->in_ch + c];
+    for (int o = 0; o < d->stem_ch; ++o) stem[(size_t)d->stem_ch * d->in_ch * K + o] = (float)b[o];
+    net->stem_lconv = (d->window + 2 * (K / 2) - K) / d->stem_stride + 1;
+    net->stem_lout = d->stem_pool ? (net->stem_lconv + 2 - 3) / 2 + 1 : net->stem_lconv;
+    net->macs = (int64_t)net->stem_lconv * d->stem_ch * d->in_ch * K;
+    net->layer_macs.push_back(net->macs);
+    net->act_elems = (int64_t)net->stem_lout * d->stem_ch;
+
+    std::vector<double> wscale_d;
+    int L = net->stem_lout, C = d->stem_ch, slot_x = 0, n_slots = 1;
+    auto add_conv = [&](int c_in, int c_out, int kw, int s, int l_in, int relu, int in_buf, int out_buf,
+                        int res_buf, int amax_in) -> bool {
+        ConvOp op{};
+        op.c_in = c_in; op.c_out = c_out; op.kw = kw; op.s = s; op.l_in = l_in;
+        op.l_out = (l_in + 2 * (kw / 2) - kw) / s + 1;
+        op.relu = relu; op.in_buf = in_buf; op.out_buf = out_buf; op.res_buf = res_buf;
+        op.amax_in = amax_in;
+        op.amax_out = n_slots++;
+        op.w_off = wfold.size();
+        op.b_off = bias.size();
+        op.fn = pick_conv(prec, kw, s, c_in, c_out);
+        if (!op.fn) {
+            set_error("no conv kernel for kw=%d stride=%d c_in=%d c_out=%d", kw, s, c_in, c_out);
+            return false;
+        }
+        if (!take_conv(c_out, c_in, kw, w, b)) { set_error("params too short"); return false; }
+        wfold.insert(wfold.end(), w.begin(), w.end());
+        for (int o = 0; o < c_out; ++o) bias.push_back((float)b[o]);
+        net->macs += (int64_t)op.l_out * c_out * c_in * kw;
+        net->layer_macs.push_back((int64_t)op.l_out * c_out * c_in * kw);
+        net->act_elems = std::max<int64_t>(net->act_elems, (int64_t)op.l_out * c_out);
+        net->ops.push_back(op);
+        return true;
+    };
+    for (int st = 0; st < d->n_stages; ++st) {
+        for (int bl = 0; bl < d->blocks[st]; ++bl) {
+            const int wdt = d->widths[st];
+            const int s = (bl == 0 && st > 0) ? 2 : 1;
+            const bool proj = s != 1 || C != wdt;
+            if (!add_conv(C, wdt, K, s, L, 1, BX, BR, -1, slot_x)) { free_net(net); return AF_EINVAL; }
+            const int slot_r = net->ops.back().amax_out;
+            const int l_out = net->ops.back().l_out;
+            // conv2 runs after the projection: its parameters follow conv2's in the
+            // parameter order, so read conv2 first and swap the two ops afterwards
+            if (!add_conv(wdt, wdt, K, 1, l_out, 1, BR, BX, proj ? BP : BX, slot_r)) { free_net(net); return AF_EINVAL; }
+            if (proj) {
+                if (!add_conv(C, wdt, 1, s, L, 0, BX, BP, -1, slot_x)) { free_net(net); return AF_EINVAL; }
+                std::swap(net->ops[net->ops.size() - 1], net->ops[net->ops.size() - 2]);
+                std::swap(net->layer_macs[net->layer_macs.size() - 1], net->layer_macs[net->layer_macs.size() - 2]);
+                slot_x = net->ops.back().amax_out;   // conv2 (now last) writes the block output
+            } else {
+                slot_x = net->ops.back().amax_out;
+            }
+            C = wdt;
+            L = l_out;
+        }
+    }
+    if (p + C + 1 != p_end) {
+        free_net(net);
+        set_error("params length mismatch: %lld left for an FC of %d inputs", (long long)(p_end - p), C);
+        return AF_EINVAL;
+    }
+    if (256 % C != 0) { free_net(net); set_error("last width must divide 256"); return AF_EINVAL; }
+    std::vector<float> fc(C);
+    for (int c = 0; c < C; ++c) fc[c] = (float)p[c];
+    net->fc_b = (float)p[C];
+    net->macs += C;
+    net->layer_macs.push_back(C);
+    net->last_L = L;
+    net->last_C = C;
+    net->n_slots = n_slots;
+
+    // ---- storage conversion -------------------------------------------------------------------
+    std::vector<unsigned char> wbytes;
+    std::vector<float> wsc;
+    if (prec == AF_F32) {
+        wbytes.resize(wfold.size() * 4);
+        float* f = (float*)wbytes.data();
+        for (size_t i = 0; i < wfold.size(); ++i) f[i] = (float)wfold[i];
+    } else if (prec == AF_BF16) {
+        wbytes.resize(wfold.size() * 2);
+        uint16_t* h = (uint16_t*)wbytes.data();
+        for (size_t i = 0; i < wfold.size(); ++i) h[i] = host_bf16_bits(wfold[i]);
+    } else {
+        wbytes.resize(wfold.size());
+        wsc.resize(bias.size());
+        for (const ConvOp& op : net->ops) {
+            const size_t per = (size_t)op.kw * op.c_in;
+            for (int o = 0; o < op.c_out; ++o) {
+                const double* row = &wfold[op.w_off + o * per];
+                double mx = 0.0;
+                for (size_t i = 0; i < per; ++i) mx = std::max(mx, std::fabs(row[i]));
+                const double sc = mx > 0 ? mx / 448.0 : 1.0;
+                wsc[op.b_off + o] = (float)sc;
+                for (size_t i = 0; i < per; ++i) wbytes[op.w_off + o * per + i] = host_e4m3_bits(row[i] / sc);
+            }
+        }
+    }
+    // element offsets -> byte offsets are applied at launch (w_off counts elements)
+    auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
+        if (bytes == 0) return true;
+        if (hipMalloc(dst, bytes) != hipSuccess) return false;
+        return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
+    };
+    if (!upload(&net->d_w, wbytes.data(), wbytes.size()) ||
+        !upload((void**)&net->d_b, bias.data(), bias.size() * 4) ||
+        !upload((void**)&net->d_stem, stem.data(), stem.size() * 4) ||
+        !upload((void**)&net->d_fc, fc.data(), fc.size() * 4) ||
+        (prec == AF_FP8 && !upload((void**)&net->d_ws, wsc.data(), wsc.size() * 4))) {
+        free_net(net);
+        set_error("device allocation/upload of the weights failed");
+        return AF_ENOMEM;
+    }
+    *out = net;
+    return AF_OK;
+}
+
+extern "C" void af_net_destroy(af_net* net) { free_net(net); }
+extern "C" int64_t af_net_macs(const af_net* net) { return net ? net->macs : 0; }
+
+namespace {
+size_t buf_bytes(const af_net* net, int64_t batch) {
+    return align_up((size_t)batch * net->act_elems * act_size(net->prec), 256);
+}
+size_t amax_bytes(const af_net* net, int64_t batch) {
+    return net->prec == AF_FP8 ? align_up((size_t)net->n_slots * batch * 4, 256) : 0;
+}
+}  // namespace
+
+extern "C" size_t af_score_workspace_bytes(const af_net* net, int64_t batch) {
+    if (!net || batch < 1) return 0;
+    return 3 * buf_bytes(net, batch) + amax_bytes(net, batch);
+}
+
+extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                                      int64_t stride, int64_t n_windows, const int64_t* ch_shift, int64_t wrap,
+                                      float* logits, void* ws, size_t ws_bytes, af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && y, "net and y must be non-null");
+    AF_CHECK_ARG(logits || n_windows == 0, "logits must be non-null");
+    AF_CHECK_ARG(n_ch == net->desc.in_ch, "n_ch %lld does not match the net's %d inputs", (long long)n_ch, net->desc.in_ch);
+    AF_CHECK_ARG(n >= 1 && ld_y >= n && stride >= 1 && n_windows >= 0, "need n >= 1, ld_y >= n, stride >= 1, n_windows >= 0");
+    AF_CHECK_ARG(wrap >= 0 && wrap <= n, "wrap must be in [0, n]");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    const int window = net->desc.window;
+    int64_t shift[4] = {0, 0, 0, 0};
+    for (int c = 0; c < n_ch; ++c) {
+        shift[c] = ch_shift ? ch_shift[c] : 0;
+        AF_CHECK_ARG(shift[c] >= 0, "ch_shift must be non-negative");
+        if (wrap == 0 && n_windows > 0)
+            AF_CHECK_ARG((n_windows - 1) * stride + shift[c] + window <= n,
+                         "window %lld of channel %d ends past n = %lld", (long long)(n_windows - 1), c, (long long)n);
+    }
+    if (n_windows == 0) return AF_OK;
+    int64_t batch = 0;
+    {
+        // largest batch that fits the workspace
+        int64_t lo = 0, hi = n_windows;
+        while (lo < hi) {
+            int64_t mid = (lo + hi + 1) / 2;
+            if (af_score_workspace_bytes(net, mid) <= ws_bytes) lo = mid; else hi = mid - 1;
+        }
+        batch = lo;
+    }
+    AF_CHECK_ARG(ws && batch >= 1, "workspace too small: one window needs %zu bytes", af_score_workspace_bytes(net, 1));
+    AF_CHECK_ARG(batch * net->act_elems < (1LL << 31) && batch < (1LL << 24), "batch too large");
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bb = buf_bytes(net, batch);
+    void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
+    uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
+    const size_t esz_w = net->prec == AF_F32 ? 4 : (net->prec == AF_BF16 ? 2 : 1);
+    const af_net_desc& d = net->desc;
+    af_net* mnet = const_cast<af_net*>(net);  // timing records only; the weights stay read-only
+    auto t_begin = [&](int layer, int64_t nw) -> bool {
+        if (!net->profiling) return true;
+        af_net::Rec r{layer, nw, nullptr, nullptr};
+        if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return false;
+        if (hipEventRecord(r.a, s) != hipSuccess) return false;
+        mnet->recs.push_back(r);
+        return true;
+    };
+    auto t_end = [&]() -> bool {
+        return !net->profiling || hipEventRecord(mnet->recs.back().b, s) == hipSuccess;
+    };
+
+    for (int64_t w0 = 0; w0 < n_windows; w0 += batch) {
+        const int nb = (int)std::min<int64_t>(batch, n_windows - w0);
+        if (amax) {
+            const int64_t cnt = (int64_t)net->n_slots * batch;
+            hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, amax, cnt, 0u);
+        }
+        StemArgs sa{};
+        sa.y = y; sa.ld_y = ld_y; sa.n = n; sa.stride = stride; sa.wrap = wrap; sa.first_window = w0;
+        for (int c = 0; c < 4; ++c) sa.shift[c] = shift[c];
+        sa.n_ch = (int)n_ch; sa.window = window;
+        sa.w = net->d_stem; sa.b = net->d_stem + (size_t)d.stem_ch * d.in_ch * d.kernel;
+        sa.out = buf[BX]; sa.amax_out = amax;
+        sa.C = d.stem_ch; sa.KW = d.kernel; sa.s0 = d.stem_stride; sa.pool = d.stem_pool;
+        sa.L_conv = net->stem_lconv; sa.L_out = net->stem_lout;
+        const size_t stem_lds = (size_t)n_ch * window * sizeof(float);
+        if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
+        if (net->prec == AF_F32) hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
+        else if (net->prec == AF_BF16) hipLaunchKernelGGL(stem_kernel<PBF16>, dim3(nb), dim3(256), stem_lds, s, sa);
+        else hipLaunchKernelGGL(stem_kernel<PFP8>, dim3(nb), dim3(256), stem_lds, s, sa);
+        AF_LAUNCHED();
+        t_end();
+        int layer = 0;
+        for (const ConvOp& op : net->ops) {
+            ++layer;
+            ConvArgs a{};
+            a.in = buf[op.in_buf];
+            a.out = buf[op.out_buf];
+            a.res = op.res_buf >= 0 ? buf[op.res_buf] : nullptr;
+            a.w = (const char*)net->d_w + op.w_off * esz_w;
+            a.bias = net->d_b + op.b_off;
+            a.wscale = net->d_ws ? net->d_ws + op.b_off : nullptr;
+            a.amax_in = amax ? amax + (size_t)op.amax_in * batch : nullptr;
+            a.amax_out = amax ? amax + (size_t)op.amax_out * batch : nullptr;
+            a.C_in = op.c_in; a.C_out = op.c_out; a.L_in = op.l_in; a.L_out = op.l_out;
+            a.relu = op.relu;
+            if (!t_begin(layer, nb)) { set_error("profiling event failed"); return AF_EHIP; }
+            op.fn(a, nb, s);
+            AF_LAUNCHED();
+            t_end();
+        }
+        if (!t_begin(layer + 1, nb)) { set_error("profiling event failed"); return AF_EHIP; }
+        if (net->prec == AF_F32)
+            hipLaunchKernelGGL(gap_fc_kernel<PF32>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);
+        else
+            hipLaunchKernelGGL(gap_fc_kernel<PBF16>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);
+        AF_LAUNCHED();
+        t_end();
+    }
+    return AF_OK;
+}
+
+extern "C" int64_t af_net_n_layers(const af_net* net) { return net ? (int64_t)net->layer_macs.size() : 0; }
+
+extern "C" af_status af_net_profile_begin(af_net* net) {
+    clear_error();
+    AF_CHECK_ARG(net, "net must be non-null");
+    drop_records(net);
+    net->profiling = true;
+    return AF_OK;
+}
+
+extern "C" af_status af_net_profile_end(af_net* net, int64_t n_layers, double* ms, int64_t* launches,
+                                        double* flops) {
+    clear_error();
+    AF_CHECK_ARG(net, "net must be non-null");
+    AF_CHECK_ARG(n_layers == (int64_t)net->layer_macs.size() && ms && launches && flops,
+                 "need arrays of af_net_n_layers() = %zu entries", net->layer_macs.size());
+    net->profiling = false;
+    for (int64_t i = 0; i < n_layers; ++i) { ms[i] = 0.0; launches[i] = 0; flops[i] = 0.0; }
+    for (auto& r : net->recs) {
+        float t = 0.f;
+        if (hipEventSynchronize(r.b) != hipSuccess || hipEventElapsedTime(&t, r.a, r.b) != hipSuccess) {
+            set_error("reading profiling events failed");
+            drop_records(net);
+            return AF_EHIP;
+        }
+        ms[r.layer] += t;
+        launches[r.layer] += 1;
+        flops[r.layer] += 2.0 * (double)net->layer_macs[r.layer] * (double)r.windows;
+    }
+    drop_records(net);
+    return AF_OK;
+}
