@@ -12,42 +12,83 @@ using namespace afm;
 
 namespace {
 
-using LaunchFn = void (*)(const ConvArgs&, int, hipStream_t);
+using LaunchFn = void (*)(const ConvArgs&, hipStream_t);
 
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC>
-void launch_conv(const ConvArgs& a0, int n_win, hipStream_t s) {
+// Tile geometry of one conv kernel instantiation, needed on the host to lay out
+// the weight image and to size the grid.
+struct ConvCfg {
+    LaunchFn fn = nullptr;
+    int MT = 0, NT = 0, KC = 0, KWP = 0, WMAX = 1;
+    int PB = 0;   // weight row pitch in the image (elements)
+};
+
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
+void launch_conv(const ConvArgs& a, hipStream_t s) {
     constexpr int MT = WM * TM * 16, NT = WN * TN * 16;
-    ConvArgs a = a0;
-    a.tiles_per_win = (a.L_out + MT - 1) / MT;
-    dim3 grid((unsigned)(n_win * a.tiles_per_win), (unsigned)(a.C_out / NT));
-    hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC>), grid, dim3(64 * WM * WN), 0, s, a);
+    const unsigned gx = a.wpt == 1 ? (unsigned)(a.n_win * a.tiles_per_win) : (unsigned)((a.n_win + a.wpt - 1) / a.wpt);
+    hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB>), dim3(gx, (unsigned)(a.C_out / NT)),
+                       dim3(64 * WM * WN), 0, s, a);
 }
 
-// Tile shape by output width: 16 -> 256x16, 32 -> 192x32, 64 -> 96x64, >=128 -> 96x128.
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
+ConvCfg make_cfg() {
+    ConvCfg c;
+    c.fn = launch_conv<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB>;
+    c.MT = WM * TM * 16;
+    c.NT = WN * TN * 16;
+    c.KC = KC;
+    c.KWP = ChunkGeom<KW, KC, 4 * P::KL>::KWP;
+    c.WMAX = WMAX;
+    c.PB = sizeof(typename P::Op) == 4 ? KC + 4 : KC;   // must match the kernel's PB
+    return c;
+}
+
+// FP32: 16-channel chunks, single LDS buffer (two workgroups per CU overlap
+// staging with compute); tiles 96x128, 96x64, 192x32, 256x16 by output width.
+template <int KW, int S>
+ConvCfg pick_f32(int c_out) {
+    if (c_out % 128 == 0) return make_cfg<PF32, KW, S, 2, 2, 3, 4, 16, 1, false>();
+    if (c_out == 64) return make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>();
+    if (c_out == 32) return make_cfg<PF32, KW, S, 4, 1, 3, 2, 16, 1, false>();
+    if (c_out == 16) return make_cfg<PF32, KW, S, 4, 1, 4, 1, 16, 1, false>();
+    return {};
+}
+
+// BF16 / FP8: 32-channel chunks (16 for 16-channel inputs), tiles of 192 rows
+// (up to two short windows per tile) x 128/64 columns, 256 x 32/16 for the
+// narrow layers; double-buffered LDS except for the stride-2 k7 entry convs of
+// the wide stages, whose slab is twice as tall.
 template <typename P, int KW, int S, int KC>
-LaunchFn pick_by_width(int c_out) {
-    if (c_out == 16) return launch_conv<P, KW, S, 4, 1, 4, 1, KC>;
-    if (c_out == 32) return launch_conv<P, KW, S, 4, 1, 3, 2, KC>;
-    if (c_out == 64) return launch_conv<P, KW, S, 2, 2, 3, 2, KC>;
-    if (c_out % 128 == 0) return launch_conv<P, KW, S, 2, 2, 3, 4, KC>;
-    return nullptr;
+ConvCfg pick_lowp(int c_out) {
+    constexpr bool DB_WIDE = !(KW == 7 && S == 2);
+    if (c_out % 128 == 0) return make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>();
+    if (c_out == 64) return make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>();
+    if (c_out == 32) return make_cfg<P, KW, S, 4, 1, 4, 2, KC, 1, true>();
+    if (c_out == 16) return make_cfg<P, KW, S, 4, 1, 4, 1, KC, 1, true>();
+    return {};
 }
 
 template <typename P, int KC>
-LaunchFn pick_shape(int kw, int s, int c_out) {
-    if (kw == 7 && s == 1) return pick_by_width<P, 7, 1, KC>(c_out);
-    if (kw == 7 && s == 2) return c_out >= 64 ? pick_by_width<P, 7, 2, KC>(c_out) : nullptr;
-    if (kw == 1 && s == 2) return c_out >= 64 ? pick_by_width<P, 1, 2, KC>(c_out) : nullptr;
-    return nullptr;
+ConvCfg pick_shape_lowp(int kw, int s, int c_out) {
+    if (kw == 7 && s == 1) return pick_lowp<P, 7, 1, KC>(c_out);
+    if (kw == 7 && s == 2) return c_out >= 64 ? pick_lowp<P, 7, 2, KC>(c_out) : ConvCfg{};
+    if (kw == 1 && s == 2) return c_out >= 64 ? pick_lowp<P, 1, 2, KC>(c_out) : ConvCfg{};
+    return {};
 }
 
-LaunchFn pick_conv(af_precision p, int kw, int s, int c_in, int c_out) {
-    if (p == AF_F32) return c_in % 16 == 0 ? pick_shape<PF32, 16>(kw, s, c_out) : nullptr;
+ConvCfg pick_conv(af_precision p, int kw, int s, int c_in, int c_out) {
+    if (p == AF_F32) {
+        if (c_in % 16 != 0) return {};
+        if (kw == 7 && s == 1) return pick_f32<7, 1>(c_out);
+        if (kw == 7 && s == 2) return c_out >= 64 ? pick_f32<7, 2>(c_out) : ConvCfg{};
+        if (kw == 1 && s == 2) return c_out >= 64 ? pick_f32<1, 2>(c_out) : ConvCfg{};
+        return {};
+    }
     const bool kc32 = c_in % 32 == 0;
-    if (kw == 1 && !kc32) return nullptr;  // a 1x1 chunk must fill a whole 32-deep MFMA
-    if (p == AF_BF16)
-        return kc32 ? pick_shape<PBF16, 32>(kw, s, c_out) : (c_in % 16 == 0 ? pick_shape<PBF16, 16>(kw, s, c_out) : nullptr);
-    return kc32 ? pick_shape<PFP8, 32>(kw, s, c_out) : (c_in % 16 == 0 ? pick_shape<PFP8, 16>(kw, s, c_out) : nullptr);
+    if (kw == 1 && !kc32) return {};  // a 1x1 chunk must fill a whole 32-deep MFMA
+    if (!kc32 && c_in % 16 != 0) return {};
+    if (p == AF_BF16) return kc32 ? pick_shape_lowp<PBF16, 32>(kw, s, c_out) : pick_shape_lowp<PBF16, 16>(kw, s, c_out);
+    return kc32 ? pick_shape_lowp<PFP8, 32>(kw, s, c_out) : pick_shape_lowp<PFP8, 16>(kw, s, c_out);
 }
 
 // ---- host rounding onto BF16 / E4M3 grids (round to nearest even) -----------------
@@ -85,8 +126,10 @@ struct ConvOp {
     int c_in, c_out, kw, s, l_in, l_out, relu;
     int in_buf, out_buf, res_buf;  // res_buf < 0: none
     int amax_in, amax_out;         // FP8 slots
-    size_t w_off, b_off;
-    LaunchFn fn;
+    size_t w_off, b_off;           // folded weights [C_out][KW][C_in] / bias offsets
+    size_t img_off;                // weight image offset (elements)
+    ConvCfg cfg;
+    int wpt, tt, tiles_per_win;
 };
 
 }  // namespace
@@ -196,7 +239,6 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     net->layer_macs.push_back(net->macs);
     net->act_elems = (int64_t)net->stem_lout * d->stem_ch;
 
-    std::vector<double> wscale_d;
     int L = net->stem_lout, C = d->stem_ch, slot_x = 0, n_slots = 1;
     auto add_conv = [&](int c_in, int c_out, int kw, int s, int l_in, int relu, int in_buf, int out_buf,
                         int res_buf, int amax_in) -> bool {
@@ -208,12 +250,21 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         op.amax_out = n_slots++;
         op.w_off = wfold.size();
         op.b_off = bias.size();
-        op.fn = pick_conv(prec, kw, s, c_in, c_out);
-        if (!op.fn) {
+        op.cfg = pick_conv(prec, kw, s, c_in, c_out);
+        if (!op.cfg.fn) {
             set_error("no conv kernel for kw=%d stride=%d c_in=%d c_out=%d", kw, s, c_in, c_out);
             return false;
         }
         if (!take_conv(c_out, c_in, kw, w, b)) { set_error("params too short"); return false; }
+        // M tiling: several short windows per tile, or several tiles per window
+        const int MT = op.cfg.MT;
+        if (op.l_out >= MT) {
+            op.wpt = 1; op.tt = MT; op.tiles_per_win = (op.l_out + MT - 1) / MT;
+        } else if (MT % op.l_out == 0 && op.l_out % 16 == 0 && MT / op.l_out <= op.cfg.WMAX) {
+            op.wpt = MT / op.l_out; op.tt = op.l_out; op.tiles_per_win = 1;
+        } else {
+            op.wpt = 1; op.tt = MT; op.tiles_per_win = 1;
+        }
         wfold.insert(wfold.end(), w.begin(), w.end());
         for (int o = 0; o < c_out; ++o) bias.push_back((float)b[o]);
         net->macs += (int64_t)op.l_out * c_out * c_in * kw;
@@ -260,20 +311,15 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     net->last_C = C;
     net->n_slots = n_slots;
 
-    // ---- storage conversion -------------------------------------------------------------------
-    std::vector<unsigned char> wbytes;
+    // ---- weight images in storage precision ------------------------------------------------
+    // per conv: [C_out/NT][C_in/KC][KWP][NT][PB], taps >= KW and pad columns zero:
+    // each chunk is the exact LDS image a workgroup copies with direct loads
     std::vector<float> wsc;
-    if (prec == AF_F32) {
-        wbytes.resize(wfold.size() * 4);
-        float* f = (float*)wbytes.data();
-        for (size_t i = 0; i < wfold.size(); ++i) f[i] = (float)wfold[i];
-    } else if (prec == AF_BF16) {
-        wbytes.resize(wfold.size() * 2);
-        uint16_t* h = (uint16_t*)wbytes.data();
-        for (size_t i = 0; i < wfold.size(); ++i) h[i] = host_bf16_bits(wfold[i]);
-    } else {
-        wbytes.resize(wfold.size());
-        wsc.resize(bias.size());
+    if (prec == AF_FP8) {
+        wsc.assign(bias.size(), 1.f);
+    }
+    std::vector<double> wscale_full(bias.size(), 1.0);
+    if (prec == AF_FP8) {
         for (const ConvOp& op : net->ops) {
             const size_t per = (size_t)op.kw * op.c_in;
             for (int o = 0; o < op.c_out; ++o) {
@@ -281,9 +327,36 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
                 double mx = 0.0;
                 for (size_t i = 0; i < per; ++i) mx = std::max(mx, std::fabs(row[i]));
                 const double sc = mx > 0 ? mx / 448.0 : 1.0;
+                wscale_full[op.b_off + o] = sc;
                 wsc[op.b_off + o] = (float)sc;
-                for (size_t i = 0; i < per; ++i) wbytes[op.w_off + o * per + i] = host_e4m3_bits(row[i] / sc);
             }
+        }
+    }
+    const size_t esz = prec == AF_F32 ? 4 : (prec == AF_BF16 ? 2 : 1);  // bytes per stored weight
+    size_t img_total = 0;
+    for (ConvOp& op : net->ops) {
+        op.img_off = img_total;
+        img_total += (size_t)(op.c_out / op.cfg.NT) * (op.c_in / op.cfg.KC) * op.cfg.KWP * op.cfg.NT * op.cfg.PB;
+    }
+    std::vector<unsigned char> wbytes(img_total * esz, 0);
+    for (const ConvOp& op : net->ops) {
+        const int NT = op.cfg.NT, KC = op.cfg.KC, KWP = op.cfg.KWP, PB = op.cfg.PB;
+        const int n_chunks = op.c_in / KC;
+        for (int o = 0; o < op.c_out; ++o) {
+            const int nt = o / NT, n = o % NT;
+            for (int j = 0; j < op.kw; ++j)
+                for (int c = 0; c < op.c_in; ++c) {
+                    const int cc = c / KC, ci = c % KC;
+                    const size_t e = op.img_off + ((((size_t)nt * n_chunks + cc) * KWP + j) * NT + n) * PB + ci;
+                    const double v = wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
+                    if (prec == AF_F32) {
+                        ((float*)wbytes.data())[e] = (float)v;
+                    } else if (prec == AF_BF16) {
+                        ((uint16_t*)wbytes.data())[e] = host_bf16_bits(v);
+                    } else {
+                        wbytes[e] = host_e4m3_bits(v / wscale_full[op.b_off + o]);
+                    }
+                }
         }
     }
     // element offsets -> byte offsets are applied at launch (w_off counts elements)
@@ -314,6 +387,27 @@ size_t buf_bytes(const af_net* net, int64_t batch) {
 }
 size_t amax_bytes(const af_net* net, int64_t batch) {
     return net->prec == AF_FP8 ? align_up((size_t)net->n_slots * batch * 4, 256) : 0;
+}
+}  // namespace
+
+namespace {
+template <typename P>
+bool launch_stem_p(const af_net_desc& d, const StemArgs& sa, int nb, size_t lds, hipStream_t s) {
+    if (d.in_ch != 2 || d.kernel != 7) return false;
+    if (d.stem_ch == 16 && d.stem_stride == 1 && !d.stem_pool)
+        hipLaunchKernelGGL((stem2_kernel<P, 16, 1, false>), dim3(nb), dim3(256), lds, s, sa);
+    else if (d.stem_ch == 32 && d.stem_stride == 2 && d.stem_pool)
+        hipLaunchKernelGGL((stem2_kernel<P, 32, 2, true>), dim3(nb), dim3(256), lds, s, sa);
+    else if (d.stem_ch == 32 && d.stem_stride == 1 && !d.stem_pool)
+        hipLaunchKernelGGL((stem2_kernel<P, 32, 1, false>), dim3(nb), dim3(256), lds, s, sa);
+    else
+        return false;
+    return true;
+}
+bool launch_stem(af_precision p, const af_net_desc& d, const StemArgs& sa, int nb, size_t lds, hipStream_t s) {
+    if (p == AF_F32) return launch_stem_p<PF32>(d, sa, nb, lds, s);
+    if (p == AF_BF16) return launch_stem_p<PBF16>(d, sa, nb, lds, s);
+    return launch_stem_p<PFP8>(d, sa, nb, lds, s);
 }
 }  // namespace
 
@@ -391,9 +485,11 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
         sa.L_conv = net->stem_lconv; sa.L_out = net->stem_lout;
         const size_t stem_lds = (size_t)n_ch * window * sizeof(float);
         if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
-        if (net->prec == AF_F32) hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
-        else if (net->prec == AF_BF16) hipLaunchKernelGGL(stem_kernel<PBF16>, dim3(nb), dim3(256), stem_lds, s, sa);
-        else hipLaunchKernelGGL(stem_kernel<PFP8>, dim3(nb), dim3(256), stem_lds, s, sa);
+        if (!launch_stem(net->prec, d, sa, nb, stem_lds, s)) {
+            if (net->prec == AF_F32) hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
+            else if (net->prec == AF_BF16) hipLaunchKernelGGL(stem_kernel<PBF16>, dim3(nb), dim3(256), stem_lds, s, sa);
+            else hipLaunchKernelGGL(stem_kernel<PFP8>, dim3(nb), dim3(256), stem_lds, s, sa);
+        }
         AF_LAUNCHED();
         t_end();
         int layer = 0;
@@ -403,15 +499,19 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
             a.in = buf[op.in_buf];
             a.out = buf[op.out_buf];
             a.res = op.res_buf >= 0 ? buf[op.res_buf] : nullptr;
-            a.w = (const char*)net->d_w + op.w_off * esz_w;
+            a.w = (const char*)net->d_w + op.img_off * esz_w;
             a.bias = net->d_b + op.b_off;
             a.wscale = net->d_ws ? net->d_ws + op.b_off : nullptr;
             a.amax_in = amax ? amax + (size_t)op.amax_in * batch : nullptr;
             a.amax_out = amax ? amax + (size_t)op.amax_out * batch : nullptr;
             a.C_in = op.c_in; a.C_out = op.c_out; a.L_in = op.l_in; a.L_out = op.l_out;
             a.relu = op.relu;
+            a.n_win = nb;
+            a.wpt = op.wpt;
+            a.tt = op.tt;
+            a.tiles_per_win = op.tiles_per_win;
             if (!t_begin(layer, nb)) { set_error("profiling event failed"); return AF_EHIP; }
-            op.fn(a, nb, s);
+            op.cfg.fn(a, s);
             AF_LAUNCHED();
             t_end();
         }

@@ -88,21 +88,44 @@ struct ConvArgs {
     const void* in;        // [B][L_in][C_in]  (P::Act)
     void* out;             // [B][L_out][C_out] (P::Act)
     const void* res;       // residual [B][L_out][C_out] or null
-    const void* w;         // [C_out][KW][C_in] (P::Op)
+    const void* w;         // weight image: [C_out/NT][C_in/KC][KWP][NT][PB] (P::Op), PB >= KC padded
     const float* bias;     // [C_out]
     const float* wscale;   // FP8: [C_out]
     const uint32_t* amax_in;   // FP8: [B] max |input| bit patterns
     uint32_t* amax_out;        // FP8: [B]
-    int C_in, C_out, L_in, L_out, tiles_per_win;
+    int C_in, C_out, L_in, L_out;
+    int n_win;             // windows in this batch
+    int wpt;               // windows per M tile (tile rows = wpt x tt)
+    int tt;                // output times per window per tile (multiple of 16)
+    int tiles_per_win;     // M tiles per window when wpt == 1
     int relu;
 };
 
-// Implicit-GEMM conv on 16x16xMK MFMA tiles.  Workgroup = WM x WN waves; each
-// wave owns TM x TN tiles.  Tile rows are output times of one window, columns
-// are output channels.  K is walked in chunks of KC input channels x all taps:
-// the chunk's input rows (slab) and weights are staged in LDS, then every tap
-// j reads the slab shifted by j rows.
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC>
+template <int KW, int KC, int MK>
+struct ChunkGeom {
+    static constexpr int KCH = KW * KC;
+    static constexpr int KPAD = (KCH + MK - 1) / MK * MK;
+    static constexpr int KWP = KPAD / KC;
+};
+
+// Two packed BF16 words (4 values) -> 4 E4M3 bytes after scaling by sc.
+__device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, float sc) {
+    const uint32_t b0 = f32_to_e4m3(__uint_as_float(lo2 << 16) * sc);
+    const uint32_t b1 = f32_to_e4m3(__uint_as_float(lo2 & 0xFFFF0000u) * sc);
+    const uint32_t b2 = f32_to_e4m3(__uint_as_float(hi2 << 16) * sc);
+    const uint32_t b3 = f32_to_e4m3(__uint_as_float(hi2 & 0xFFFF0000u) * sc);
+    return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+}
+
+// Implicit-GEMM conv on 16x16xMK MFMA tiles.
+// Workgroup = WM x WN waves, each wave TM x TN tiles of 16x16 outputs.  The M
+// tile covers `wpt` windows x `tt` output times; the N tile NT output channels.
+// K is walked in chunks of KC input channels x all KW taps.  Per chunk the
+// input rows of every window in the tile (the slab, rows t*S - (KW-1)/2 ...)
+// and the chunk's weights are staged in LDS with 16-byte loads; tap j then
+// reads the slab shifted by j rows.  With DB the next chunk is fetched into
+// registers while the current one is multiplied (two LDS buffers).
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
 __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     using Op = typename P::Op;
     using Act = typename P::Act;
@@ -111,66 +134,153 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     constexpr int MT = WM * TM * 16;
     constexpr int NT = WN * TN * 16;
     constexpr int NTH = 64 * WM * WN;
-    constexpr int KCH = KW * KC;                        // real k per chunk
-    constexpr int KPAD = (KCH + MK - 1) / MK * MK;      // padded to whole MFMAs
+    using G = ChunkGeom<KW, KC, MK>;
+    constexpr int KPAD = G::KPAD, KWP = G::KWP;
     static_assert(KPAD % KC == 0, "chunk padding must be whole taps");
     static_assert(KC % KL == 0, "lane k-run must stay inside one tap");
-    constexpr int KWP = KPAD / KC;                      // taps incl. zero padding
-    constexpr int ROWS = (MT - 1) * S + KWP;            // slab rows
-    constexpr int PA = KC + (sizeof(Op) == 4 ? 1 : 16 / (int)sizeof(Op));  // padded pitch (elements)
-    constexpr int PB = PA;
+    constexpr int OPB = (int)sizeof(Op);
+    constexpr int PA = KC + 16 / OPB;           // slab row pitch in elements (16 B of padding)
+    constexpr int PB = OPB == 4 ? KC + 4 : KC;  // weight row pitch (FP32 lanes read 4 B: pad)
     constexpr int PAD = (KW - 1) / 2;
-    __shared__ __attribute__((aligned(16))) Op slab[ROWS * PA];
-    __shared__ __attribute__((aligned(16))) Op wl[KWP * NT * PB];
+    // rows of all windows' slabs: wpt windows need (MT - wpt) S + wpt KWP rows,
+    // largest at wpt = WMAX when KWP >= S and at wpt = 1 otherwise (1x1, stride 2)
+    constexpr int ROWS_W1 = (MT - 1) * S + KWP;
+    constexpr int ROWS_WMAX = (MT - WMAX) * S + WMAX * KWP;
+    constexpr int SLAB_ROWS = ROWS_W1 > ROWS_WMAX ? ROWS_W1 : ROWS_WMAX;
+    constexpr int SLAB_EL = SLAB_ROWS * PA;
+    constexpr int W_EL = KWP * NT * PB;
+    constexpr int NBUF = DB ? 2 : 1;
+    // slab: 16-byte vectors through registers; weights: the chunk's LDS image
+    // (padding included) copied with direct global->LDS 16-byte loads
+    constexpr int AE = 16 / (int)sizeof(Act);   // activations per 16-byte load
+    constexpr int AV_ROW = KC / AE;             // vectors per slab row
+    static_assert(KC % AE == 0, "slab rows must be whole 16-byte vectors");
+    constexpr int AV_MAX = SLAB_ROWS * AV_ROW;
+    constexpr int RA = (AV_MAX + NTH - 1) / NTH;  // slab vectors per thread (upper bound)
+    constexpr int W_BYTES = W_EL * OPB;           // one chunk's weight image
+    static_assert(W_BYTES % 16 == 0 && (SLAB_EL * OPB) % 16 == 0, "16-byte LDS regions");
+    constexpr int W_INST = (W_BYTES + 1023) / 1024;  // wave-wide 1 KB copies per chunk
+    constexpr int NWAVES = WM * WN;
+    __shared__ __attribute__((aligned(16))) Op smem[NBUF * (SLAB_EL + W_EL)];
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wave = tid >> 6;
     const int wm = wave % WM, wn = wave / WM;
-    const int win = blockIdx.x / a.tiles_per_win;
-    const int t0 = (blockIdx.x % a.tiles_per_win) * MT;
-    const int n0 = blockIdx.y * NT;
-    const Act* in = (const Act*)a.in + (size_t)win * a.L_in * a.C_in;
-    const Op* wg = (const Op*)a.w;
+    const int g = lane >> 4;     // lane group: k sub-range
+    const int r16 = lane & 15;   // row (A) / column (B) inside a 16x16 tile
+    const int wpt = a.wpt, tt = a.tt;
+    const int srows = (tt - 1) * S + KWP;   // slab rows per window
+    int win0, t0;
+    if (wpt == 1) {
+        win0 = blockIdx.x / a.tiles_per_win;
+        t0 = (blockIdx.x % a.tiles_per_win) * tt;
+    } else {
+        win0 = blockIdx.x * wpt;
+        t0 = 0;
+    }
+    const int nt = blockIdx.y;
+    const int n0 = nt * NT;
+    const int n_chunks = a.C_in / KC;
+    const Act* in = (const Act*)a.in;
+    const char* wimg = (const char*)a.w + (size_t)nt * n_chunks * W_BYTES;
 
-    float inv_a = 1.f, s_a = 1.f;
-    if constexpr (P::kFP8) {
-        float amax = __uint_as_float(a.amax_in[win]);
-        if (!(amax > 0.f)) amax = 448.f;
-        inv_a = 448.f / amax;
-        s_a = amax / 448.f;
+    // FP8: per-window activation scales of the windows in this tile
+    float inv_a[WMAX], s_a[WMAX];
+#pragma unroll
+    for (int w = 0; w < WMAX; ++w) {
+        inv_a[w] = 1.f;
+        s_a[w] = 1.f;
+        if constexpr (P::kFP8) {
+            if (w < wpt && win0 + w < a.n_win) {
+                float amax = __uint_as_float(a.amax_in[win0 + w]);
+                if (!(amax > 0.f)) amax = 448.f;
+                inv_a[w] = 448.f / amax;
+                s_a[w] = amax / 448.f;
+            }
+        }
     }
 
+    const int av_count = wpt * srows * AV_ROW;
+    uint4 ra[RA];
     f4v acc[TM][TN];
 #pragma unroll
     for (int i = 0; i < TM; ++i)
 #pragma unroll
         for (int j = 0; j < TN; ++j) acc[i][j] = f4v{0.f, 0.f, 0.f, 0.f};
 
-    const int g = lane >> 4;     // lane group: k sub-range
-    const int r16 = lane & 15;   // row (A) / column (B) inside a 16x16 tile
+    // slab row offsets of this lane's A rows (window-relative layout)
+    int arow[TM];
+#pragma unroll
+    for (int i = 0; i < TM; ++i) {
+        const int row = (wm * TM + i) * 16 + r16;
+        const int w = row / tt, t = row % tt;
+        arow[i] = (w * srows + t * S) * PA;
+    }
 
-    for (int cc = 0; cc < a.C_in; cc += KC) {
-        // stage the slab: rows t0*S - PAD + r, channels cc .. cc+KC
-        for (int e = tid; e < ROWS * KC; e += NTH) {
-            const int r = e / KC, c = e % KC;
-            const int gr = t0 * S - PAD + r;
-            float v = 0.f;
-            if (gr >= 0 && gr < a.L_in) v = act_to_f32<P>(in[(size_t)gr * a.C_in + cc + c]);
-            if constexpr (P::kFP8) slab[r * PA + c] = f32_to_e4m3(v * inv_a);
-            else if constexpr (sizeof(Op) == 4) slab[r * PA + c] = v;
-            else slab[r * PA + c] = f32_to_bf16_bits(v);
+#define AFM_FETCH(CC)                                                                              \
+    {                                                                                              \
+        _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
+            const int v = tid + i * NTH;                                                           \
+            uint4 x = make_uint4(0u, 0u, 0u, 0u);                                                  \
+            if (v < av_count) {                                                                    \
+                const int q = v % AV_ROW;                                                          \
+                const int rr = v / AV_ROW;                                                         \
+                const int w = rr / srows, r = rr % srows;                                          \
+                const int gr = t0 * S - PAD + r;                                                   \
+                const int win = win0 + w;                                                          \
+                if (win < a.n_win && gr >= 0 && gr < a.L_in)                                       \
+                    x = *(const uint4*)(in + ((size_t)win * a.L_in + gr) * a.C_in + (CC) * KC + q * AE); \
+            }                                                                                      \
+            ra[i] = x;                                                                             \
+        }                                                                                          \
+    }
+#define AFM_WLOAD(CC, BUF)                                                                         \
+    {                                                                                              \
+        const char* src_ = wimg + (size_t)(CC) * W_BYTES;                                          \
+        char* dst_ = (char*)(smem + (BUF) * (SLAB_EL + W_EL) + SLAB_EL);                           \
+        for (int i = wave; i < W_INST; i += NWAVES) {                                              \
+            const int o = i * 1024 + lane * 16;                                                    \
+            if (W_BYTES % 1024 == 0 || o < W_BYTES)                                                \
+                __builtin_amdgcn_global_load_lds((__attribute__((address_space(1))) void*)(src_ + o), \
+                                                 (__attribute__((address_space(3))) void*)(dst_ + i * 1024), 16, 0, 0); \
+        }                                                                                          \
+    }
+#define AFM_STASH(BUF)                                                                             \
+    {                                                                                              \
+        Op* slab_ = smem + (BUF) * (SLAB_EL + W_EL);                                               \
+        _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
+            const int v = tid + i * NTH;                                                           \
+            if (v < av_count) {                                                                    \
+                const int q = v % AV_ROW;                                                          \
+                const int rr = v / AV_ROW;                                                         \
+                Op* dst = slab_ + rr * PA + q * AE;                                                \
+                if constexpr (P::kFP8) {                                                           \
+                    const int w = rr / srows;                                                      \
+                    float sc = inv_a[0];                                                           \
+                    _Pragma("unroll") for (int u = 1; u < WMAX; ++u) sc = (w == u) ? inv_a[u] : sc; \
+                    *(uint2*)dst = make_uint2(pack_e4m3x4(ra[i].x, ra[i].y, sc),                    \
+                                              pack_e4m3x4(ra[i].z, ra[i].w, sc));                   \
+                } else {                                                                           \
+                    *(uint4*)dst = ra[i];                                                          \
+                }                                                                                  \
+            }                                                                                      \
+        }                                                                                          \
+    }
+
+    AFM_FETCH(0)
+    AFM_WLOAD(0, 0)
+    AFM_STASH(0)
+    __builtin_amdgcn_s_waitcnt(0);
+    __syncthreads();
+    for (int cc = 0; cc < n_chunks; ++cc) {
+        const int buf = DB ? (cc & 1) : 0;
+        if (DB && cc + 1 < n_chunks) {
+            AFM_FETCH(cc + 1)
+            AFM_WLOAD(cc + 1, buf ^ 1)
         }
-        // stage weights: [tap][n][c] for the chunk, zero for padded taps
-        for (int e = tid; e < KWP * NT * KC; e += NTH) {
-            const int c = e % KC;
-            const int n = (e / KC) % NT;
-            const int j = e / (KC * NT);
-            Op v = (Op)0;
-            if (j < KW) v = wg[((size_t)(n0 + n) * KW + j) * a.C_in + cc + c];
-            wl[(j * NT + n) * PB + c] = v;
-        }
-        __syncthreads();
+        const Op* slab = smem + buf * (SLAB_EL + W_EL);
+        const Op* wl = slab + SLAB_EL;
 #pragma unroll 2
         for (int ks = 0; ks < KPAD; ks += MK) {
             const int k = ks + g * KL;
@@ -178,39 +288,56 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             const Op* ab[TM];
             const Op* bb[TN];
 #pragma unroll
-            for (int i = 0; i < TM; ++i) {
-                const int row = (wm * TM + i) * 16 + r16;
-                ab[i] = &slab[(row * S + j) * PA + c];
-            }
+            for (int i = 0; i < TM; ++i) ab[i] = slab + arow[i] + j * PA + c;
 #pragma unroll
-            for (int jn = 0; jn < TN; ++jn) {
-                const int col = (wn * TN + jn) * 16 + r16;
-                bb[jn] = &wl[(j * NT + col) * PB + c];
-            }
+            for (int jn = 0; jn < TN; ++jn) bb[jn] = wl + (j * NT + (wn * TN + jn) * 16 + r16) * PB + c;
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
                 for (int jn = 0; jn < TN; ++jn) mfma_step<P>(acc[i][jn], ab[i], bb[jn]);
         }
-        __syncthreads();
+        if (DB) {
+            if (cc + 1 < n_chunks) AFM_STASH(buf ^ 1)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        } else if (cc + 1 < n_chunks) {
+            __syncthreads();
+            AFM_FETCH(cc + 1)
+            AFM_WLOAD(cc + 1, 0)
+            AFM_STASH(0)
+            __builtin_amdgcn_s_waitcnt(0);
+            __syncthreads();
+        }
     }
+#undef AFM_FETCH
+#undef AFM_WLOAD
+#undef AFM_STASH
 
-    // epilogue: dequant, bias, residual, ReLU, store, FP8 amax
-    Act* out = (Act*)a.out + (size_t)win * a.L_out * a.C_out;
-    const Act* res = a.res ? (const Act*)a.res + (size_t)win * a.L_out * a.C_out : nullptr;
-    float vmax = 0.f;
+    // epilogue: dequant, bias, residual, ReLU, store, FP8 amax per window
 #pragma unroll
-    for (int jn = 0; jn < TN; ++jn) {
-        const int col = n0 + (wn * TN + jn) * 16 + r16;
-        const float bcol = a.bias[col];
-        float deq = 1.f;
-        if constexpr (P::kFP8) deq = s_a * a.wscale[col];
+    for (int i = 0; i < TM; ++i) {
+        const int row0 = (wm * TM + i) * 16;        // 16 rows of one window
+        const int w = row0 / tt;
+        const int win = win0 + w;
+        const bool wvalid = win < a.n_win;
+        Act* out = (Act*)a.out + (size_t)win * a.L_out * a.C_out;
+        const Act* res = a.res ? (const Act*)a.res + (size_t)win * a.L_out * a.C_out : nullptr;
+        float vmax = 0.f;
 #pragma unroll
-        for (int i = 0; i < TM; ++i) {
+        for (int jn = 0; jn < TN; ++jn) {
+            const int col = n0 + (wn * TN + jn) * 16 + r16;
+            const float bcol = a.bias[col];
+            float deq = 1.f;
+            if constexpr (P::kFP8) {
+                float sw = s_a[0];
+#pragma unroll
+                for (int u = 1; u < WMAX; ++u) sw = (w == u) ? s_a[u] : sw;
+                deq = sw * a.wscale[col];
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
-                const int t = t0 + (wm * TM + i) * 16 + g * 4 + r;
-                if (t < a.L_out) {
+                const int t = t0 + (row0 % tt) + g * 4 + r;
+                if (wvalid && t < a.L_out) {
                     float v = P::kFP8 ? fmaf(acc[i][jn][r], deq, bcol) : acc[i][jn][r] + bcol;
                     const size_t o = (size_t)t * a.C_out + col;
                     if (res) v += act_to_f32<P>(res[o]);
@@ -221,11 +348,11 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                 }
             }
         }
-    }
-    if constexpr (P::kFP8) {
-        if (a.amax_out) {
-            for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
-            if (lane == 0) atomicMax(&a.amax_out[win], __float_as_uint(vmax));
+        if constexpr (P::kFP8) {
+            if (a.amax_out) {
+                for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+                if (lane == 0 && wvalid) atomicMax(&a.amax_out[win], __float_as_uint(vmax));
+            }
         }
     }
 }
@@ -281,6 +408,85 @@ __global__ void __launch_bounds__(256) stem_kernel(StemArgs a) {
         const Act sv = f32_to_act<P>(best);
         out[e] = sv;
         vmax = fmaxf(vmax, act_to_f32<P>(sv));
+    }
+    if constexpr (P::kFP8) {
+        for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(&a.amax_out[b], __float_as_uint(vmax));
+    }
+}
+
+// Stem for two detectors and kernel 7, one thread per output time with all C
+// channels in registers; weights are uniform across the workgroup (scalar
+// loads).  With POOL each thread evaluates the three conv outputs 2p-1..2p+1
+// under its max-pool window.  One workgroup per window, samples staged in LDS.
+template <typename P, int C, int S0, bool POOL>
+__global__ void __launch_bounds__(256) stem2_kernel(StemArgs a) {
+    using Act = typename P::Act;
+    constexpr int KW = 7, PADS = 3, NCH = 2;
+    constexpr int QN = POOL ? 3 : 1;
+    constexpr int NIN = (QN - 1) * S0 + KW;   // input samples per channel per thread
+    extern __shared__ float xs[];             // [NCH][window]
+    const int b = blockIdx.x;
+    const int64_t wi = a.first_window + b;
+    const int W = a.window;
+    for (int e = threadIdx.x; e < NCH * W; e += 256) {
+        const int c = e / W, t = e % W;
+        int64_t p = wi * a.stride + a.shift[c] + t;
+        if (a.wrap > 0) p %= a.wrap;
+        xs[e] = a.y[c * a.ld_y + p];
+    }
+    __syncthreads();
+    Act* out = (Act*)a.out + (size_t)b * a.L_out * C;
+    const float* __restrict__ wt = a.w;   // [C][NCH][KW]
+    const float* __restrict__ bs = a.b;
+    float vmax = 0.f;
+    for (int p = threadIdx.x; p < a.L_out; p += 256) {
+        const int q0 = POOL ? 2 * p - 1 : p;
+        const int i0 = q0 * S0 - PADS;        // first input sample
+        float xin[NCH][NIN];
+#pragma unroll
+        for (int ci = 0; ci < NCH; ++ci)
+#pragma unroll
+            for (int u = 0; u < NIN; ++u) {
+                const int ti = i0 + u;
+                xin[ci][u] = (ti >= 0 && ti < W) ? xs[ci * W + ti] : 0.f;
+            }
+        float res[C];
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            float best = 0.f;   // ReLU output >= 0; an out-of-range pool position never wins
+#pragma unroll
+            for (int q = 0; q < QN; ++q) {
+                float sacc = bs[c];
+#pragma unroll
+                for (int ci = 0; ci < NCH; ++ci)
+#pragma unroll
+                    for (int j = 0; j < KW; ++j) sacc = fmaf(wt[(c * NCH + ci) * KW + j], xin[ci][q * S0 + j], sacc);
+                const int qq = q0 + q;
+                if (!POOL || (qq >= 0 && qq < a.L_conv)) best = fmaxf(best, sacc);
+            }
+            res[c] = best;
+        }
+        Act* o = out + (size_t)p * C;
+        if constexpr (sizeof(Act) == 4) {
+#pragma unroll
+            for (int c = 0; c < C; c += 4) {
+                *(float4*)(o + c) = make_float4(res[c], res[c + 1], res[c + 2], res[c + 3]);
+                vmax = fmaxf(vmax, fmaxf(fmaxf(res[c], res[c + 1]), fmaxf(res[c + 2], res[c + 3])));
+            }
+        } else {
+#pragma unroll
+            for (int c = 0; c < C; c += 8) {
+                uint32_t u4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const uint16_t lo = f32_to_bf16_bits(res[c + 2 * e]), hi = f32_to_bf16_bits(res[c + 2 * e + 1]);
+                    u4[e] = (uint32_t)lo | ((uint32_t)hi << 16);
+                    vmax = fmaxf(vmax, fmaxf(bf16_bits_to_f32(lo), bf16_bits_to_f32(hi)));
+                }
+                *(uint4*)(o + c) = make_uint4(u4[0], u4[1], u4[2], u4[3]);
+            }
+        }
     }
     if constexpr (P::kFP8) {
         for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
