@@ -134,6 +134,14 @@ void af_net_destroy(af_net* net);
 /* Total conv + FC multiply-accumulates per window. */
 int64_t af_net_macs(const af_net* net);
 
+/* Whole-network path.  For the 16-channel two-block net (stem 2->16 k7 s1,
+ * one stage of two BasicBlocks) in BF16, scoring runs as one persistent kernel
+ * that keeps every activation in LDS (on by default).  af_net_fused reports
+ * whether it is active; af_net_set_fused(net, 0) selects the layer-by-layer
+ * kernels instead (AF_EINVAL if enabling it on a net without the path). */
+int af_net_fused(const af_net* net);
+af_status af_net_set_fused(af_net* net, int enable);
+
 /* Number of timed layers: stem, each conv in execution order, GAP+FC head. */
 int64_t af_net_n_layers(const af_net* net);
 /* Kernel timing (a tracing aid, Sec. VIII reports per-stage latencies).
@@ -141,7 +149,8 @@ int64_t af_net_n_layers(const af_net* net);
  * event pair around each kernel it launches (on the call's stream).  end()
  * waits for those events and writes, per layer index (0 = stem, 1.. = convs
  * in execution order, last = head): total milliseconds, launch count and
- * algorithmic FLOPs (2 x MACs x windows).  Arrays have af_net_n_layers()
+ * algorithmic FLOPs (2 x MACs x windows).  With the whole-network kernel the
+ * entire network's time and FLOPs are reported under layer 1.  Arrays have af_net_n_layers()
  * entries.  Not thread-safe with concurrent scoring on the same net. */
 af_status af_net_profile_begin(af_net* net);
 af_status af_net_profile_end(af_net* net, int64_t n_layers, double* ms, int64_t* launches, double* flops);
@@ -158,6 +167,28 @@ af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int6
                            int64_t n, int64_t stride, int64_t n_windows,
                            const int64_t* ch_shift, int64_t wrap, float* logits,
                            void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Timeslide background (Sec. IX: H1 held fixed, L1 shifted in 1 s steps to
+ * build background livetime).  Segment s occupies samples
+ * [seg_off[s], seg_off[s] + seg_len[s]) of every channel of y (host arrays).
+ * For slide k and window i of segment s, channel 0 reads samples
+ * i*stride + t and every other channel reads (i*stride + shifts[k] + t) mod
+ * seg_len[s], t < window, both relative to seg_off[s] (circular shift inside
+ * the segment).  A segment holds (seg_len - window)/stride + 1 windows (none if
+ * shorter than a window).  logits are written segment-major, then slide, then
+ * window: [sum_s n_slides * n_w(s)] floats, af_timeslide_n_windows() of them.
+ * The (segment, slide) work table is copied to the workspace first (this call
+ * blocks until that small copy is done); all windows of all pairs then run in
+ * shared batches.
+ * ------------------------------------------------------------------------ */
+int64_t af_timeslide_n_windows(const int64_t* seg_len, int64_t n_seg, int64_t n_slides, int64_t window,
+                               int64_t stride);
+size_t af_timeslide_workspace_bytes(const af_net* net, int64_t n_seg, int64_t n_slides, int64_t batch);
+af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                              const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
+                              const int64_t* shifts, int64_t n_slides, int64_t stride, float* logits,
+                              void* ws, size_t ws_bytes, af_stream stream);
 
 /* ------------------------------------------------------------------------
  * Integration (Sec. II: predictions integrated with a 1 s top-hat filter).

@@ -14,7 +14,8 @@ import torch
 
 from ._lib import AframeError, NetDesc, check, lib
 
-__all__ = ["psd_estimate", "whiten", "Net", "integrate", "pack_params", "AframeError", "lib"]
+__all__ = ["psd_estimate", "whiten", "Net", "integrate", "pack_params", "score_timeslides", "timeslide_n_windows",
+           "AframeError", "lib"]
 
 AF_IN_F64, AF_IN_F32 = 0, 1
 PRECISIONS = {"f32": 0, "bf16": 1, "fp8": 2}
@@ -147,6 +148,15 @@ class Net:
         return lib().af_net_macs(self._h)
 
     @property
+    def fused(self):
+        """True when scoring runs as the whole-network persistent kernel."""
+        return bool(lib().af_net_fused(self._h))
+
+    @fused.setter
+    def fused(self, enable):
+        check(lib().af_net_set_fused(self._h, int(bool(enable))))
+
+    @property
     def n_layers(self):
         return lib().af_net_n_layers(self._h)
 
@@ -186,6 +196,35 @@ class Net:
                                      ctypes.cast(sh, ctypes.c_void_p) if sh is not None else None, wrap,
                                      _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
         return out
+
+
+def _i64(v):
+    a = np.ascontiguousarray(np.asarray(v, dtype=np.int64))
+    return a, a.ctypes.data_as(ctypes.c_void_p)
+
+
+def timeslide_n_windows(seg_len, n_slides, window=3072, stride=2048):
+    a, p = _i64(seg_len)
+    return int(lib().af_timeslide_n_windows(p, len(a), n_slides, window, stride))
+
+
+def score_timeslides(net, y, seg_off, seg_len, shifts, stride=2048, batch=4096, out=None, ws=None, stream=None):
+    """Logits of every (segment, slide, window) of a timeslide background
+    (af_score_timeslides); y [n_ch, n] float32 holds the whitened segments."""
+    _check_dev(y, "y", (torch.float32,))
+    n_ch, n = y.shape
+    so, pso = _i64(seg_off)
+    sl, psl = _i64(seg_len)
+    sh, psh = _i64(shifts)
+    tot = timeslide_n_windows(sl, len(sh), net.window, stride)
+    if out is None:
+        out = torch.empty(tot, dtype=torch.float32, device=y.device)
+    if ws is None:
+        ws = _workspace(lib().af_timeslide_workspace_bytes(net._h, len(so), len(sh), max(1, min(batch, tot))),
+                        y.device)
+    check(lib().af_score_timeslides(net._h, _ptr(y), n_ch, y.stride(0), n, pso, psl, len(so), psh, len(sh), stride,
+                                    _ptr(out), _ptr(ws), ws.numel(), _stream(stream)))
+    return out
 
 
 def integrate(p, width, out=None, stream=None):

@@ -33,11 +33,17 @@ SIGNATURES = {
     "af_net_macs": (c_i64, [c_vp]),
     "af_score_workspace_bytes": (c_sz, [c_vp, c_i64]),
     "af_net_n_layers": (c_i64, [c_vp]),
+    "af_net_fused": (c_int, [c_vp]),
+    "af_net_set_fused": (c_int, [c_vp, c_int]),
     "af_net_profile_begin": (c_int, [c_vp]),
     "af_net_profile_end": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "af_score_windows": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp,
                                  c_sz, c_vp]),
     "af_integrate": (c_int, [c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "af_timeslide_n_windows": (c_i64, [c_vp, c_i64, c_i64, c_i64, c_i64]),
+    "af_timeslide_workspace_bytes": (c_sz, [c_vp, c_i64, c_i64, c_i64]),
+    "af_score_timeslides": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_vp,
+                                    c_vp, c_sz, c_vp]),
 }
 
 _lib = None

@@ -6,7 +6,7 @@
 #include <new>
 #include <vector>
 
-#include "net_kernels.h"
+#include "fused_tiny.h"
 
 using namespace afm;
 
@@ -20,6 +20,8 @@ struct ConvCfg {
     LaunchFn fn = nullptr;
     int MT = 0, NT = 0, KC = 0, KWP = 0, WMAX = 1;
     int PB = 0;   // weight row pitch in the image (elements)
+    int KL = 1;   // k values per lane per MFMA (swizzle unit)
+    int SWR = 0;  // rows per swizzle step (0: no swizzle)
 };
 
 template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
@@ -39,7 +41,10 @@ ConvCfg make_cfg() {
     c.KC = KC;
     c.KWP = ChunkGeom<KW, KC, 4 * P::KL>::KWP;
     c.WMAX = WMAX;
-    c.PB = sizeof(typename P::Op) == 4 ? KC + 4 : KC;   // must match the kernel's PB
+    constexpr int OPB = (int)sizeof(typename P::Op);
+    c.PB = OPB == 4 ? KC + 4 : KC;   // these three must match the kernel's PB, KL, SWR
+    c.KL = P::KL;
+    c.SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
     return c;
 }
 
@@ -155,8 +160,14 @@ struct af_net {
     struct Rec {
         int layer;
         int64_t windows;
+        int64_t macs;   // per window
         hipEvent_t a, b;
     };
+    // whole-network persistent kernel for the 16-channel two-block net (BF16)
+    bool fused_ok = false, fused_on = false;
+    int n_cu = 0;
+    uint16_t* d_wfused = nullptr;   // [4][16][128]
+    float* d_bfused = nullptr;      // [4][16]
     std::vector<Rec> recs;
     std::vector<int64_t> layer_macs;  // per window: stem, convs..., gap/fc
 };
@@ -180,6 +191,8 @@ void free_net(af_net* n) {
     if (n->d_ws) (void)hipFree(n->d_ws);
     if (n->d_stem) (void)hipFree(n->d_stem);
     if (n->d_fc) (void)hipFree(n->d_fc);
+    if (n->d_wfused) (void)hipFree(n->d_wfused);
+    if (n->d_bfused) (void)hipFree(n->d_bfused);
     delete n;
 }
 }  // namespace
@@ -341,13 +354,16 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     std::vector<unsigned char> wbytes(img_total * esz, 0);
     for (const ConvOp& op : net->ops) {
         const int NT = op.cfg.NT, KC = op.cfg.KC, KWP = op.cfg.KWP, PB = op.cfg.PB;
+        const int KLs = op.cfg.KL, SWR = op.cfg.SWR, SWU = KC / op.cfg.KL;
         const int n_chunks = op.c_in / KC;
         for (int o = 0; o < op.c_out; ++o) {
             const int nt = o / NT, n = o % NT;
             for (int j = 0; j < op.kw; ++j)
                 for (int c = 0; c < op.c_in; ++c) {
                     const int cc = c / KC, ci = c % KC;
-                    const size_t e = op.img_off + ((((size_t)nt * n_chunks + cc) * KWP + j) * NT + n) * PB + ci;
+                    const int row = j * NT + n;   // row of the chunk's LDS image
+                    const int cs = SWR ? (((ci / KLs) ^ ((row / SWR) & (SWU - 1))) * KLs + ci % KLs) : ci;
+                    const size_t e = op.img_off + (((size_t)nt * n_chunks + cc) * KWP * NT + row) * PB + cs;
                     const double v = wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
                     if (prec == AF_F32) {
                         ((float*)wbytes.data())[e] = (float)v;
@@ -374,7 +390,44 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         set_error("device allocation/upload of the weights failed");
         return AF_ENOMEM;
     }
+    // fused whole-network path: stem 2->16 k7 s1, one stage of two 16-channel
+    // blocks, BF16
+    const bool tiny = d->in_ch == 2 && d->stem_ch == 16 && d->stem_stride == 1 && !d->stem_pool &&
+                      d->n_stages == 1 && d->widths[0] == 16 && d->blocks[0] == 2 && net->ops.size() == 4;
+    if (tiny && prec == AF_BF16) {
+        std::vector<uint16_t> wf(4 * 16 * 128, 0);
+        std::vector<float> bf(4 * 16);
+        for (int l = 0; l < 4; ++l) {
+            const ConvOp& op = net->ops[l];
+            for (int o = 0; o < 16; ++o) {
+                for (int j = 0; j < 7; ++j)
+                    for (int c = 0; c < 16; ++c)
+                        wf[((size_t)l * 16 + o) * 128 + j * 16 + c] =
+                            host_bf16_bits(wfold[op.w_off + ((size_t)o * 7 + j) * 16 + c]);
+                bf[l * 16 + o] = bias[op.b_off + o];
+            }
+        }
+        if (!upload((void**)&net->d_wfused, wf.data(), wf.size() * 2) ||
+            !upload((void**)&net->d_bfused, bf.data(), bf.size() * 4)) {
+            free_net(net);
+            set_error("device allocation/upload of the fused weights failed");
+            return AF_ENOMEM;
+        }
+        net->fused_ok = net->fused_on = true;
+    }
+    if (hipDeviceGetAttribute(&net->n_cu, hipDeviceAttributeMultiprocessorCount, net->device) != hipSuccess)
+        net->n_cu = 256;
     *out = net;
+    return AF_OK;
+}
+
+extern "C" int af_net_fused(const af_net* net) { return net && net->fused_ok && net->fused_on ? 1 : 0; }
+
+extern "C" af_status af_net_set_fused(af_net* net, int enable) {
+    clear_error();
+    AF_CHECK_ARG(net, "net must be non-null");
+    AF_CHECK_ARG(!enable || net->fused_ok, "this net has no fused path (needs the 16-channel two-block net in BF16)");
+    net->fused_on = enable != 0;
     return AF_OK;
 }
 
@@ -416,6 +469,12 @@ extern "C" size_t af_score_workspace_bytes(const af_net* net, int64_t batch) {
     return 3 * buf_bytes(net, batch) + amax_bytes(net, batch);
 }
 
+namespace {
+af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
+                        int64_t n_windows, const int64_t* shift, int64_t wrap, const int64_t* table, int n_entries,
+                        float* logits, void* ws, size_t ws_bytes, hipStream_t s);
+}
+
 extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
                                       int64_t stride, int64_t n_windows, const int64_t* ch_shift, int64_t wrap,
                                       float* logits, void* ws, size_t ws_bytes, af_stream stream) {
@@ -438,6 +497,44 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
                          "window %lld of channel %d ends past n = %lld", (long long)(n_windows - 1), c, (long long)n);
     }
     if (n_windows == 0) return AF_OK;
+    return score_batches(net, y, ld_y, n, stride, n_windows, shift, wrap, nullptr, 0, logits, ws, ws_bytes,
+                         (hipStream_t)stream);
+}
+
+namespace {
+// Score n_windows windows in passes of the largest batch the workspace holds.
+// Plain mode (table == null): window i of channel c starts at i*stride + shift[c]
+// (mod wrap).  Timeslide mode: addressing comes from the device work table.
+af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
+                        int64_t n_windows, const int64_t* shift, int64_t wrap, const int64_t* table, int n_entries,
+                        float* logits, void* ws, size_t ws_bytes, hipStream_t s) {
+    const int window = net->desc.window;
+    const int64_t n_ch = net->desc.in_ch;
+    af_net* mnet0 = const_cast<af_net*>(net);   // timing records only
+    if (net->fused_ok && net->fused_on) {
+        FusedTinyArgs fa{};
+        StemArgs& sa = fa.st;
+        sa.y = y; sa.ld_y = ld_y; sa.n = n; sa.stride = stride; sa.wrap = wrap; sa.first_window = 0;
+        sa.table = table; sa.n_entries = n_entries;
+        for (int c = 0; c < 4; ++c) sa.shift[c] = c < n_ch ? shift[c] : 0;
+        sa.n_ch = (int)n_ch; sa.window = window;
+        sa.w = net->d_stem; sa.b = net->d_stem + (size_t)16 * 2 * 7;
+        fa.wconv = net->d_wfused; fa.bconv = net->d_bfused; fa.fc_w = net->d_fc; fa.fc_b = net->fc_b;
+        fa.logits = logits; fa.n_windows = n_windows;
+        const int64_t grid = std::min<int64_t>(n_windows, (int64_t)2 * net->n_cu);
+        af_net::Rec r{1, n_windows, net->macs, nullptr, nullptr};
+        if (net->profiling) {
+            if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
+                hipEventRecord(r.a, s) != hipSuccess) { set_error("profiling event failed"); return AF_EHIP; }
+        }
+        hipLaunchKernelGGL(fused_tiny_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, s, fa);
+        AF_LAUNCHED();
+        if (net->profiling) {
+            if (hipEventRecord(r.b, s) != hipSuccess) { set_error("profiling event failed"); return AF_EHIP; }
+            mnet0->recs.push_back(r);
+        }
+        return AF_OK;
+    }
     int64_t batch = 0;
     {
         // largest batch that fits the workspace
@@ -450,7 +547,6 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
     }
     AF_CHECK_ARG(ws && batch >= 1, "workspace too small: one window needs %zu bytes", af_score_workspace_bytes(net, 1));
     AF_CHECK_ARG(batch * net->act_elems < (1LL << 31) && batch < (1LL << 24), "batch too large");
-    hipStream_t s = (hipStream_t)stream;
     const size_t bb = buf_bytes(net, batch);
     void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
     uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
@@ -459,7 +555,7 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
     af_net* mnet = const_cast<af_net*>(net);  // timing records only; the weights stay read-only
     auto t_begin = [&](int layer, int64_t nw) -> bool {
         if (!net->profiling) return true;
-        af_net::Rec r{layer, nw, nullptr, nullptr};
+        af_net::Rec r{layer, nw, net->layer_macs[layer], nullptr, nullptr};
         if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess) return false;
         if (hipEventRecord(r.a, s) != hipSuccess) return false;
         mnet->recs.push_back(r);
@@ -477,6 +573,7 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
         }
         StemArgs sa{};
         sa.y = y; sa.ld_y = ld_y; sa.n = n; sa.stride = stride; sa.wrap = wrap; sa.first_window = w0;
+        sa.table = table; sa.n_entries = n_entries;
         for (int c = 0; c < 4; ++c) sa.shift[c] = shift[c];
         sa.n_ch = (int)n_ch; sa.window = window;
         sa.w = net->d_stem; sa.b = net->d_stem + (size_t)d.stem_ch * d.in_ch * d.kernel;
@@ -526,6 +623,71 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
     return AF_OK;
 }
 
+}  // namespace
+
+size_t timeslide_table_bytes(int64_t n_seg, int64_t n_slides) {
+    return align_up((size_t)(n_seg * n_slides) * 4 * sizeof(int64_t), 256);
+}
+
+extern "C" int64_t af_timeslide_n_windows(const int64_t* seg_len, int64_t n_seg, int64_t n_slides, int64_t window,
+                                          int64_t stride) {
+    if (!seg_len || n_seg < 0 || n_slides < 0 || window < 1 || stride < 1) return -1;
+    int64_t tot = 0;
+    for (int64_t sg = 0; sg < n_seg; ++sg)
+        if (seg_len[sg] >= window) tot += n_slides * ((seg_len[sg] - window) / stride + 1);
+    return tot;
+}
+
+extern "C" size_t af_timeslide_workspace_bytes(const af_net* net, int64_t n_seg, int64_t n_slides, int64_t batch) {
+    if (!net || n_seg < 1 || n_slides < 1 || batch < 1) return 0;
+    return timeslide_table_bytes(n_seg, n_slides) + af_score_workspace_bytes(net, batch);
+}
+
+extern "C" af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                                         const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
+                                         const int64_t* shifts, int64_t n_slides, int64_t stride, float* logits,
+                                         void* ws, size_t ws_bytes, af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && y && seg_off && seg_len && shifts, "net, y, seg_off, seg_len and shifts must be non-null");
+    AF_CHECK_ARG(n_ch == net->desc.in_ch, "n_ch %lld does not match the net's %d inputs", (long long)n_ch, net->desc.in_ch);
+    AF_CHECK_ARG(n >= 1 && ld_y >= n && stride >= 1 && n_seg >= 1 && n_slides >= 1,
+                 "need n >= 1, ld_y >= n, stride >= 1, n_seg >= 1, n_slides >= 1");
+    AF_CHECK_ARG(n_seg * n_slides < (1LL << 30), "too many (segment, slide) pairs");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    const int64_t window = net->desc.window;
+    std::vector<int64_t> tab((size_t)(n_seg * n_slides) * 4);
+    int64_t tot = 0;
+    for (int64_t sg = 0; sg < n_seg; ++sg) {
+        AF_CHECK_ARG(seg_off[sg] >= 0 && seg_len[sg] >= 0 && seg_off[sg] + seg_len[sg] <= n,
+                     "segment %lld [%lld, +%lld) is not inside [0, n)", (long long)sg, (long long)seg_off[sg],
+                     (long long)seg_len[sg]);
+        const int64_t nw = seg_len[sg] >= window ? (seg_len[sg] - window) / stride + 1 : 0;
+        for (int64_t k = 0; k < n_slides; ++k) {
+            AF_CHECK_ARG(shifts[k] >= 0, "shifts must be non-negative");
+            int64_t* e = &tab[(size_t)(sg * n_slides + k) * 4];
+            e[0] = seg_off[sg];
+            e[1] = seg_len[sg];
+            e[2] = seg_len[sg] > 0 ? shifts[k] % seg_len[sg] : 0;
+            e[3] = tot;
+            tot += nw;
+        }
+    }
+    AF_CHECK_ARG(logits || tot == 0, "logits must be non-null");
+    if (tot == 0) return AF_OK;
+    const size_t tb = timeslide_table_bytes(n_seg, n_slides);
+    AF_CHECK_ARG(ws && ws_bytes >= tb + af_score_workspace_bytes(net, 1),
+                 "workspace too small: need at least %zu bytes", tb + af_score_workspace_bytes(net, 1));
+    hipStream_t s = (hipStream_t)stream;
+    // the table is a few KB; a blocking copy keeps its host storage simple
+    AF_HIP(hipMemcpyAsync(ws, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
+    AF_HIP(hipStreamSynchronize(s));
+    int64_t zero[4] = {0, 0, 0, 0};
+    return score_batches(net, y, ld_y, n, stride, tot, zero, 0, (const int64_t*)ws, (int)(n_seg * n_slides), logits,
+                         (char*)ws + tb, ws_bytes - tb, s);
+}
+
 extern "C" int64_t af_net_n_layers(const af_net* net) { return net ? (int64_t)net->layer_macs.size() : 0; }
 
 extern "C" af_status af_net_profile_begin(af_net* net) {
@@ -553,7 +715,7 @@ extern "C" af_status af_net_profile_end(af_net* net, int64_t n_layers, double* m
         }
         ms[r.layer] += t;
         launches[r.layer] += 1;
-        flops[r.layer] += 2.0 * (double)net->layer_macs[r.layer] * (double)r.windows;
+        flops[r.layer] += 2.0 * (double)r.macs * (double)r.windows;
     }
     drop_records(net);
     return AF_OK;

@@ -141,6 +141,11 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     constexpr int OPB = (int)sizeof(Op);
     constexpr int PA = KC + 16 / OPB;           // slab row pitch in elements (16 B of padding)
     constexpr int PB = OPB == 4 ? KC + 4 : KC;  // weight row pitch (FP32 lanes read 4 B: pad)
+    // BF16/FP8 weight rows are not padded; instead the KL-element units of row
+    // r are XOR-swizzled by (r / SWR) & (KC/KL - 1), so that the 16 rows one
+    // MFMA operand read touches fall in distinct LDS banks
+    constexpr int SWU = KC / KL;                                    // units per row
+    constexpr int SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
     constexpr int PAD = (KW - 1) / 2;
     // rows of all windows' slabs: wpt windows need (MT - wpt) S + wpt KWP rows,
     // largest at wpt = WMAX when KWP >= S and at wpt = 1 otherwise (1x1, stride 2)
@@ -281,7 +286,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
         }
         const Op* slab = smem + buf * (SLAB_EL + W_EL);
         const Op* wl = slab + SLAB_EL;
-#pragma unroll 2
+#pragma unroll
         for (int ks = 0; ks < KPAD; ks += MK) {
             const int k = ks + g * KL;
             const int j = k / KC, c = k % KC;
@@ -290,7 +295,11 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
 #pragma unroll
             for (int i = 0; i < TM; ++i) ab[i] = slab + arow[i] + j * PA + c;
 #pragma unroll
-            for (int jn = 0; jn < TN; ++jn) bb[jn] = wl + (j * NT + (wn * TN + jn) * 16 + r16) * PB + c;
+            for (int jn = 0; jn < TN; ++jn) {
+                const int row = j * NT + (wn * TN + jn) * 16 + r16;
+                const int cs = SWR ? (((c / KL) ^ ((row / (SWR ? SWR : 1)) & (SWU - 1))) * KL) : c;
+                bb[jn] = wl + row * PB + cs;
+            }
 #pragma unroll
             for (int i = 0; i < TM; ++i)
 #pragma unroll
@@ -361,6 +370,10 @@ struct StemArgs {
     const float* y;          // whitened series [n_ch][ld_y]
     int64_t ld_y, n, stride, wrap, first_window;
     int64_t shift[4];
+    // timeslide work table (device): per entry {segment offset, segment length,
+    // shift of channels >= 1, first global window}; null for plain windows
+    const int64_t* table;
+    int n_entries;
     int n_ch, window;
     const float* w;          // folded stem weights [C][n_ch][KW] (FP32)
     const float* b;          // [C]
@@ -368,6 +381,43 @@ struct StemArgs {
     uint32_t* amax_out;      // FP8: [B]
     int C, KW, s0, pool, L_conv, L_out;
 };
+
+// Where window `wi` reads channel c: sample (start[c] + t) mod wrap (no mod
+// when wrap == 0) of y[c] + base.  Plain mode: start = wi*stride + shift[c].
+// Timeslide mode: the entry holding wi gives a segment [base, base + len);
+// channel 0 starts at i*stride and the others at i*stride + shift, both
+// circular within the segment.
+struct WinAddr {
+    int64_t base, wrap;
+    int64_t start[4];
+};
+
+__device__ __forceinline__ WinAddr window_addr(const StemArgs& a, int64_t wi) {
+    WinAddr w;
+    if (a.table) {
+        int lo = 0, hi = a.n_entries - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (a.table[4 * mid + 3] <= wi) lo = mid; else hi = mid - 1;
+        }
+        const int64_t* e = a.table + 4 * lo;
+        const int64_t i0 = (wi - e[3]) * a.stride;
+        w.base = e[0];
+        w.wrap = e[1];
+        for (int c = 0; c < 4; ++c) w.start[c] = c == 0 ? i0 : i0 + e[2];
+    } else {
+        w.base = 0;
+        w.wrap = a.wrap;
+        for (int c = 0; c < 4; ++c) w.start[c] = wi * a.stride + a.shift[c];
+    }
+    return w;
+}
+
+__device__ __forceinline__ int64_t window_sample(const WinAddr& w, int c, int t) {
+    int64_t p = w.start[c] + t;
+    if (w.wrap > 0) p %= w.wrap;
+    return w.base + p;
+}
 
 // Stem conv (vector FP32 arithmetic), ReLU, optional max-pool k3 s2 p1.
 // One workgroup per window; the window's samples are staged in LDS.
@@ -377,11 +427,10 @@ __global__ void __launch_bounds__(256) stem_kernel(StemArgs a) {
     extern __shared__ float xs[];  // [n_ch][window]
     const int b = blockIdx.x;
     const int64_t wi = a.first_window + b;
+    const WinAddr wa = window_addr(a, wi);
     for (int e = threadIdx.x; e < a.n_ch * a.window; e += 256) {
         const int c = e / a.window, t = e % a.window;
-        int64_t p = wi * a.stride + a.shift[c] + t;
-        if (a.wrap > 0) p %= a.wrap;
-        xs[e] = a.y[c * a.ld_y + p];
+        xs[e] = a.y[c * a.ld_y + window_sample(wa, c, t)];
     }
     __syncthreads();
     const int pad = (a.KW - 1) / 2;
@@ -429,11 +478,10 @@ __global__ void __launch_bounds__(256) stem2_kernel(StemArgs a) {
     const int b = blockIdx.x;
     const int64_t wi = a.first_window + b;
     const int W = a.window;
+    const WinAddr wa = window_addr(a, wi);
     for (int e = threadIdx.x; e < NCH * W; e += 256) {
         const int c = e / W, t = e % W;
-        int64_t p = wi * a.stride + a.shift[c] + t;
-        if (a.wrap > 0) p %= a.wrap;
-        xs[e] = a.y[c * a.ld_y + p];
+        xs[e] = a.y[c * a.ld_y + window_sample(wa, c, t)];
     }
     __syncthreads();
     Act* out = (Act*)a.out + (size_t)b * a.L_out * C;

@@ -120,3 +120,28 @@ def test_fp8_resnet_error_bound():
     got = P.Net(RESNET_ARCH, params, "fp8").score_windows(dev(y), 128, 12).cpu().numpy()
     ref = oracle_logits(params, RESNET_ARCH, y, 128, 12)
     assert np.abs(got - ref).max() < 0.3
+
+
+def test_fused_tiny_matches_layer_path():
+    # the persistent whole-network kernel and the layer-by-layer kernels agree
+    P = need_gpu()
+    banner("fused tiny bf16 vs layer path")
+    params = make_params(TINY_ARCH, seed=21)
+    y = dev(series(3072 + 128 * 40, seed=22))
+    net = P.Net(TINY_ARCH, params, "bf16")
+    assert net.fused
+    a = net.score_windows(y, 128).cpu().numpy()
+    net.fused = False
+    b = net.score_windows(y, 128, batch=16).cpu().numpy()
+    net.fused = True
+    assert np.abs(a - b).max() < 2e-5
+    ref = oracle_logits(params, TINY_ARCH, y.cpu().numpy(), 128, len(a), precision="bf16")
+    assert np.abs(a - ref).max() < EMU_TOL["bf16"]
+
+
+def test_fused_unavailable_for_fp32():
+    P = need_gpu()
+    net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=1), "f32")
+    assert not net.fused
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        net.fused = True

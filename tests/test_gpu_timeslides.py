@@ -1,0 +1,57 @@
+"""GPU parity: timeslide background scoring (af_score_timeslides) against the
+oracle applied to explicitly shifted segments."""
+import numpy as np
+import pytest
+
+import oracle
+from synth import TINY_ARCH, make_params
+from tests.gpu_util import banner, dev, need_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+def oracle_timeslides(params, arch, y, seg_off, seg_len, shifts, stride):
+    out = []
+    for o, L in zip(seg_off, seg_len):
+        seg = y[:, o:o + L].astype(np.float64)
+        for k in shifts:
+            w = oracle.unfold_windows(seg, arch.window, stride, np.array([0, k % L]), L)
+            out.append(oracle.net_forward(params, arch, w) if len(w) else np.zeros(0))
+    return np.concatenate(out)
+
+
+@pytest.mark.parametrize("prec,tol", [("f32", 2e-5), ("bf16", 3e-2)])
+def test_timeslides_vs_oracle(prec, tol):
+    P = need_gpu()
+    banner(f"timeslides {prec}")
+    params = make_params(TINY_ARCH, seed=11)
+    rng = np.random.default_rng(12)
+    seg_off, seg_len = [100, 9000, 14500], [8000, 5000, 2000]    # the last one is shorter than a window
+    n = 16600
+    y = rng.standard_normal((2, n)).astype(np.float32)
+    shifts = [2048, 4096, 6144 + 3]
+    net = P.Net(TINY_ARCH, params, prec)
+    got = P.score_timeslides(net, dev(y), seg_off, seg_len, shifts, stride=1024, batch=7).cpu().numpy()
+    ref = oracle_timeslides(params, TINY_ARCH, y, seg_off, seg_len, shifts, 1024)
+    assert got.shape == ref.shape == (P.timeslide_n_windows(seg_len, 3, 3072, 1024),)
+    assert np.abs(got - ref).max() < tol
+
+
+def test_zero_shift_equals_plain_windows():
+    P = need_gpu()
+    params = make_params(TINY_ARCH, seed=13)
+    y = np.random.default_rng(14).standard_normal((2, 12000)).astype(np.float32)
+    net = P.Net(TINY_ARCH, params, "f32")
+    ts = P.score_timeslides(net, dev(y), [1000], [10000], [0, 10000], stride=512).cpu().numpy()
+    plain = net.score_windows(dev(y[:, 1000:11000].copy()), 512).cpu().numpy()
+    nw = len(plain)
+    np.testing.assert_array_equal(ts[:nw], plain)
+    np.testing.assert_array_equal(ts[nw:], plain)     # a full-length shift is no shift
+
+
+def test_rejects_segment_outside_series():
+    P = need_gpu()
+    net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=1), "f32")
+    y = dev(np.zeros((2, 5000), np.float32))
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        P.score_timeslides(net, y, [1000], [4500], [2048])
