@@ -51,6 +51,90 @@ def cpu_baseline(x, params, arch, n_windows=384):
                       f"integration); {dt:.1f} s on the host"}
 
 
+def timeslide_leg(args, P, log):
+    """24 h in 40 lognormal segments, each whitened once (rolling 64 s PSD);
+    100 circular slides of L1 at k x 1 s; windows at 1 Hz; the 16-channel
+    2-block net in BF16 as one persistent launch replayed from a hipGraph."""
+    import torch
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from paper_2403_18661_amd.timeslides import TimeslidePlan
+    from synth import TINY_ARCH, make_params, lognormal_segments
+    from synth.noise import coloured_noise
+    fs = 2048
+    durs = lognormal_segments(seed=0)
+    net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=0), "bf16")
+    cfg = PathConfig(psd_len=64 * fs)
+    outs, seg_off, seg_len = [], [], []
+    off = 0
+    t0 = time.perf_counter()
+    for k, d in enumerate(durs):
+        x = torch.from_numpy(coloured_noise(int(d) * fs, seed=1000 + k)).cuda()
+        path = OfflinePath(net, x.shape[1], cfg, batch=1)
+        if path.n_out <= 0:
+            continue
+        path.psd_stage(x)
+        y = path.whiten_stage(x).clone()
+        outs.append(y)
+        seg_off.append(off)
+        seg_len.append(y.shape[1])
+        off += y.shape[1]
+        del x, path
+    y = torch.cat(outs, dim=1).contiguous()
+    del outs
+    torch.cuda.synchronize()
+    log(f"timeslide: {len(seg_len)} segments whitened ({off / fs / 3600:.2f} h of output) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    shifts = [k * fs for k in range(1, 101)]
+    plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=fs, graph=True)
+    for _ in range(args.warmup):
+        plan.run()
+    plan.stream.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(plan.stream)
+    for _ in range(args.steps):
+        plan.run()
+    ev1.record(plan.stream)
+    ev1.synchronize()
+    dt = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    flop = 2.0 * net.macs * plan.n_windows
+    res = {"windows_per_step": plan.n_windows, "segments": len(seg_len), "slides": len(shifts),
+           "value": plan.n_windows * args.steps / dt, "unit": "windows/s", "ms_per_step": 1e3 * dt / args.steps,
+           "dtype": "bf16", "kernel": "fused_tiny_bf16_kernel (one persistent launch, hipGraph replay)",
+           "achieved_tflops": flop / (ms * 1e-3) * 1e-12, "peak_tflops": PEAK_TFLOPS["bf16"],
+           "frac": flop / (ms * 1e-3) * 1e-12 / PEAK_TFLOPS["bf16"], "kernel_ms": ms}
+    log(f"timeslide: {res['value']:.0f} windows/s, {res['achieved_tflops']:.1f} TFLOP/s")
+    del plan, y
+    torch.cuda.empty_cache()
+    return res
+
+
+def stream_leg(args, P, log):
+    """Streaming server: S independent two-detector streams, 1 s chunks with
+    exponential inter-arrival (mean 1 s), rolling 64 s PSD every 8 s, windows
+    at 16 Hz through the ResNet in BF16, batched across streams per tick."""
+    from paper_2403_18661_amd.stream import Server, run_realtime
+    from synth import RESNET_ARCH, make_params
+    from synth.noise import coloured_noise
+    fs = 2048
+    net = P.Net(RESNET_ARCH, make_params(RESNET_ARCH, seed=0), "bf16")
+    out = {}
+    for S in [int(v) for v in args.streams.split(",")]:
+        srv = Server(net, max_streams=max(S, 1), hbm_budget=64 << 30)
+        n = int((66 + args.stream_seconds + 10) * fs)
+        data = [coloured_noise(n, seed=5000 + i) for i in range(S)]
+        for _ in range(S):
+            srv.admit()
+        st = run_realtime(srv, data, args.stream_seconds, fs=fs, seed=S, log=log)
+        st["stream_mb_each"] = srv.stream_bytes / 2 ** 20
+        out[str(S)] = st
+        log(f"stream S={S}: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+            f"{st['windows_per_s']:.0f} windows/s over {st['seconds']:.1f} s")
+        srv.close()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -60,6 +144,10 @@ def main():
     ap.add_argument("--windows", type=int, default=57600)
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-timeslide", action="store_true")
+    ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--streams", default="1,16,64")
+    ap.add_argument("--stream-seconds", type=float, default=15.0)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the path shards by windows, "
@@ -166,6 +254,12 @@ def main():
         "precisions": precisions,
         "stages_ms": h["stages_ms"],
     }
+    if not args.no_timeslide:
+        out["timeslide"] = timeslide_leg(args, P, log)
+    if not args.no_stream:
+        out["stream"] = stream_leg(args, P, log)
+        if "64" in out["stream"]:
+            out["stream_p99_ms_64"] = out["stream"]["64"]["p99_ms"]
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
         out["cpu_baseline"] = cpu_baseline(x, params, arch)

@@ -39,7 +39,8 @@ typedef enum {
     AF_EINVAL = -1,        /* bad argument or shape; nothing launched            */
     AF_ENOMEM = -2,        /* host or device allocation failed                  */
     AF_EHIP = -3,          /* HIP runtime error (message in af_last_error)      */
-    AF_EUNSUPPORTED = -4   /* valid request that this build does not implement  */
+    AF_EUNSUPPORTED = -4,  /* valid request that this build does not implement  */
+    AF_EBUDGET = -5        /* the HBM budget (or stream slots) would be exceeded */
 } af_status;
 
 typedef void* af_stream;   /* hipStream_t */
@@ -155,6 +156,20 @@ int64_t af_net_n_layers(const af_net* net);
 af_status af_net_profile_begin(af_net* net);
 af_status af_net_profile_end(af_net* net, int64_t n_layers, double* ms, int64_t* launches, double* flops);
 
+/* Conv tile autotuner.  Every conv layer has a few candidate tile shapes
+ * (rows x output channels per workgroup, LDS buffering); this times each one
+ * on `batch` windows (contents of ws are overwritten; ws must hold
+ * af_score_workspace_bytes(net, batch)) and keeps the fastest, rebuilding that
+ * layer's weight image.  Synchronous; results are unchanged up to the
+ * tile-independent per-window arithmetic (the same logits bit for bit).
+ * *n_changed (may be NULL) receives the number of layers switched. */
+af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_t ws_bytes, af_stream stream,
+                          int64_t* n_changed);
+/* Tile in use for conv layer `layer` (1 = first conv, as in the profile):
+ * rows (mt) and output channels (nt) per workgroup, candidate count, chosen index. */
+af_status af_net_layer_tile(const af_net* net, int64_t layer, int32_t* mt, int32_t* nt, int32_t* n_candidates,
+                            int32_t* chosen);
+
 /* Workspace needed to score `batch` windows per internal pass. */
 size_t af_score_workspace_bytes(const af_net* net, int64_t batch);
 /* logits[i] = net(window i) for i < n_windows.  Channel c of window i is
@@ -190,6 +205,30 @@ af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, i
                               const int64_t* shifts, int64_t n_slides, int64_t stride, float* logits,
                               void* ws, size_t ws_bytes, af_stream stream);
 
+/* Two-step form for graph capture: af_timeslide_prepare copies the work table
+ * into the workspace (and blocks for that copy); af_score_timeslides_prepared
+ * then only enqueues kernels, so it may be captured in a graph and replayed.
+ * Both take the same segments, slides, stride and workspace. */
+af_status af_timeslide_prepare(const af_net* net, const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
+                               const int64_t* shifts, int64_t n_slides, int64_t stride, int64_t n,
+                               void* ws, size_t ws_bytes, af_stream stream);
+af_status af_score_timeslides_prepared(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                                       int64_t n_seg, int64_t n_slides, int64_t stride, int64_t n_windows,
+                                       float* logits, void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Graph capture (replay of launch-bound sequences).  Every library call made
+ * on `stream` between begin and end is recorded (nothing runs); the graph is
+ * then replayed with af_graph_launch.  Captured calls must not block (use the
+ * prepared timeslide form); buffers and workspaces they use must stay
+ * allocated while the graph exists.
+ * ------------------------------------------------------------------------ */
+typedef struct af_graph af_graph;
+af_status af_graph_begin(af_stream stream);
+af_status af_graph_end(af_stream stream, af_graph** out);
+af_status af_graph_launch(af_graph* graph, af_stream stream);
+void af_graph_destroy(af_graph* graph);
+
 /* ------------------------------------------------------------------------
  * Integration (Sec. II: predictions integrated with a 1 s top-hat filter).
  * Causal right-aligned mean, valid mode:
@@ -197,6 +236,79 @@ af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, i
  * n < width writes nothing.
  * ------------------------------------------------------------------------ */
 af_status af_integrate(const float* p, int64_t n, int64_t width, float* out, af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * Streaming server (Sec. VI: clients stream strain to a snapshotter that keeps
+ * the recent state, a whitener that estimates the PSD from the first 64 s of
+ * that state, and the network; Table III: online latencies).
+ *
+ * Each admitted stream is an independent n_ch-detector series (n_ch = the
+ * net's inputs, at most 2) pushed in host chunks of at most max_chunk samples.
+ * On the device a stream keeps its recent raw strain, the PSD and whitening
+ * response of its current hop, its recent whitened output and logits.  For
+ * stream-relative sample a (0 = first pushed sample):
+ *   PSD of hop j     = Welch over samples [j*psd_hop, j*psd_hop + psd_len)
+ *   whitened y[i]    = sample psd_len + M + i, whitened with the PSD of hop
+ *                      i / psd_hop (M = fduration*fs/2), produced in blocks of
+ *                      `block` outputs once M samples past the block arrived
+ *   logit[k]         = net(y[:, k*stride : k*stride + window])
+ *   integrated[k]    = mean(logit[k .. k + integrate_width - 1])
+ * which is af_psd_estimate + af_whiten + af_score_windows + af_integrate on
+ * the stream's concatenated data.  Results depend only on the stream's own
+ * data, not on when chunks arrive or which streams share a tick.
+ *
+ * af_server_tick() takes every pending chunk (up to max_tick samples per
+ * stream), advances each stream, scores the new windows of all streams in one
+ * batched call (continuous batching) and integrates per stream; it returns
+ * when the results are in host memory.  Streams are admitted while
+ * shared + (streams + 1) * per-stream bytes <= hbm_budget (AF_EBUDGET
+ * otherwise); released streams free their memory for later admissions.
+ * push() and poll() are thread-safe and may run concurrently with a tick;
+ * admit, release and tick serialise with each other.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    double fs;                 /* 2048                                        */
+    double prescale;           /* 1e21: physical strain -> O(1)                */
+    int64_t nperseg, noverlap; /* Welch segments: 4096, 2048                   */
+    int64_t psd_len;           /* PSD background: 64 s                         */
+    int64_t psd_hop;           /* PSD update cadence: 8 s                      */
+    double fduration;          /* whitening filter length: 1 s                 */
+    double highpass;           /* 32 Hz                                        */
+    int64_t stride;            /* samples between windows: 128 (16 Hz)         */
+    int64_t integrate_width;   /* windows per 1 s: 16                          */
+    int64_t block;             /* whitening block (divides psd_hop): 2048      */
+    int64_t max_chunk;         /* largest push, samples                        */
+    int64_t max_tick;          /* samples per stream consumed per tick         */
+    int64_t max_streams;       /* stream slots                                 */
+    int64_t score_batch;       /* windows per internal scoring pass            */
+    size_t hbm_budget;         /* device bytes the server may hold             */
+} af_server_config;
+
+typedef struct af_server af_server;
+
+void af_server_default_config(af_server_config* cfg);
+/* Allocates the shared state (AF_EBUDGET if it alone exceeds hbm_budget).
+ * The net must outlive the server. */
+af_status af_server_create(const af_net* net, const af_server_config* cfg, af_server** out);
+void af_server_destroy(af_server* srv);
+size_t af_server_stream_bytes(const af_server* srv);
+size_t af_server_shared_bytes(const af_server* srv);
+af_status af_server_admit(af_server* srv, int64_t* stream_id);
+af_status af_server_release(af_server* srv, int64_t stream_id);
+/* x: host [n_ch][n] float64 physical strain (copied before return). */
+af_status af_server_push(af_server* srv, int64_t stream_id, const double* x, int64_t n);
+/* *n_windows (may be NULL) receives the number of windows scored. */
+af_status af_server_tick(af_server* srv, int64_t* n_windows);
+/* Moves up to cap results to the caller (host arrays); *first_* is the index
+ * of the first value returned (logit index k / integrated index k). */
+af_status af_server_poll(af_server* srv, int64_t stream_id, float* logits, int64_t cap_logits,
+                         int64_t* n_logits, int64_t* first_logit, float* integrated, int64_t cap_integrated,
+                         int64_t* n_integrated, int64_t* first_integrated);
+/* Latency from a chunk's push() to the tick that put integrated values it
+ * enabled on the host: p50 / p99 in ms over all such chunks, the sample
+ * count and the windows scored; reset != 0 clears them. */
+af_status af_server_stats(af_server* srv, double* p50_ms, double* p99_ms, int64_t* n_samples,
+                          int64_t* windows, int reset);
 
 #ifdef __cplusplus
 }

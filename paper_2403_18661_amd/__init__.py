@@ -175,6 +175,24 @@ class Net:
                                        la.ctypes.data_as(ctypes.c_void_p), fl.ctypes.data_as(ctypes.c_void_p)))
         return {"ms": ms, "launches": la, "flops": fl}
 
+    def autotune(self, batch=1024, ws=None, stream=None):
+        """Time every candidate tile shape per conv layer and keep the fastest
+        (af_net_autotune); returns the number of layers that changed."""
+        if ws is None:
+            ws = _workspace(self.workspace_bytes(batch), "cuda")
+        n = ctypes.c_int64()
+        check(lib().af_net_autotune(self._h, batch, _ptr(ws), ws.numel(), _stream(stream), ctypes.byref(n)))
+        return n.value
+
+    def tiles(self):
+        """[(rows, out_channels, n_candidates, chosen)] per conv layer."""
+        out = []
+        for layer in range(1, self.n_layers - 1):
+            v = [ctypes.c_int32() for _ in range(4)]
+            check(lib().af_net_layer_tile(self._h, layer, *[ctypes.byref(x) for x in v]))
+            out.append(tuple(x.value for x in v))
+        return out
+
     def workspace_bytes(self, batch):
         return lib().af_score_workspace_bytes(self._h, batch)
 

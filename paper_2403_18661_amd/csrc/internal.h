@@ -1,0 +1,21 @@
+// Library-internal entry points shared between translation units.
+#pragma once
+#include "common.h"
+
+struct af_net;
+
+namespace afm {
+af_status whiten_build_response(const double* psd, int64_t n_ch, int64_t n_psd, int64_t nperseg, double fs,
+                                double highpass, int M, float* resp, hipStream_t s);
+af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
+                       const float* resp, int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out,
+                       float* y, int64_t ld_y, hipStream_t s);
+// Score windows described by a device work table (see af_score_timeslides).
+af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
+                      int64_t n_windows, const int64_t* table, int n_entries, float* logits, void* ws,
+                      size_t ws_bytes, hipStream_t s);
+int net_window(const af_net* net);
+int net_in_ch(const af_net* net);
+int net_device(const af_net* net);
+constexpr int kWhitenBlockOut = 6146;   // outputs per 8192-point block with a 2047-tap filter
+}  // namespace afm

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "fused_tiny.h"
+#include "internal.h"
 
 using namespace afm;
 
@@ -42,58 +43,88 @@ ConvCfg make_cfg() {
     c.KWP = ChunkGeom<KW, KC, 4 * P::KL>::KWP;
     c.WMAX = WMAX;
     constexpr int OPB = (int)sizeof(typename P::Op);
-    c.PB = OPB == 4 ? KC + 4 : KC;   // these three must match the kernel's PB, KL, SWR
+    c.PB = OPB == 4 ? KC + 4 : (P::KL == 32 ? KC + 16 : KC);   // these three must match the kernel's PB, KL, SWR
     c.KL = P::KL;
     c.SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
     return c;
 }
 
+using Cands = std::vector<ConvCfg>;
+
+// Candidate tile shapes per layer class; the first is the default, the
+// autotuner (af_net_autotune) may pick another by timing.
 // FP32: 16-channel chunks, single LDS buffer (two workgroups per CU overlap
-// staging with compute); tiles 96x128, 96x64, 192x32, 256x16 by output width.
+// staging with compute).
 template <int KW, int S>
-ConvCfg pick_f32(int c_out) {
-    if (c_out % 128 == 0) return make_cfg<PF32, KW, S, 2, 2, 3, 4, 16, 1, false>();
-    if (c_out == 64) return make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>();
-    if (c_out == 32) return make_cfg<PF32, KW, S, 4, 1, 3, 2, 16, 1, false>();
-    if (c_out == 16) return make_cfg<PF32, KW, S, 4, 1, 4, 1, 16, 1, false>();
+Cands cands_f32(int c_out) {
+    if (c_out % 128 == 0)
+        return {make_cfg<PF32, KW, S, 2, 2, 3, 4, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, false>(),
+                make_cfg<PF32, KW, S, 2, 2, 2, 4, 16, 1, false>()};
+    if (c_out == 64)
+        return {make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 1, false>(),
+                make_cfg<PF32, KW, S, 2, 2, 2, 2, 16, 1, false>()};
+    if constexpr (KW == 7 && S == 1) {
+        if (c_out == 32)
+            return {make_cfg<PF32, 7, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 2, 16, 1, false>(),
+                    make_cfg<PF32, 7, 1, 2, 2, 6, 1, 16, 1, false>()};
+        if (c_out == 16)
+            return {make_cfg<PF32, 7, 1, 4, 1, 4, 1, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 1, 16, 1, false>()};
+    }
     return {};
 }
 
-// BF16 / FP8: 32-channel chunks (16 for 16-channel inputs), tiles of 192 rows
-// (up to two short windows per tile) x 128/64 columns, 256 x 32/16 for the
-// narrow layers; double-buffered LDS except for the stride-2 k7 entry convs of
-// the wide stages, whose slab is twice as tall.
+// BF16 / FP8: tiles of up to 192 rows (two short windows per tile) x 128/64
+// columns, 256 x 32/16 for the narrow layers, double-buffered LDS except where
+// the stride-2 slab would not fit twice.
 template <typename P, int KW, int S, int KC>
-ConvCfg pick_lowp(int c_out) {
-    constexpr bool DB_WIDE = !(KW == 7 && S == 2);
-    if (c_out % 128 == 0) return make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>();
-    if (c_out == 64) return make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>();
-    if (c_out == 32) return make_cfg<P, KW, S, 4, 1, 4, 2, KC, 1, true>();
-    if (c_out == 16) return make_cfg<P, KW, S, 4, 1, 4, 1, KC, 1, true>();
-    return {};
+Cands cands_lowp(int c_out) {
+    if constexpr (KC == 16) {
+        if (KW == 7 && S == 1 && c_out == 16)
+            return {make_cfg<P, 7, 1, 4, 1, 4, 1, 16, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 1, 16, 1, true>()};
+        return {};
+    } else {
+        constexpr bool DB_WIDE = !(KW == 7 && S == 2);
+        if (c_out % 128 == 0)
+            return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>()};
+        if (c_out == 64)
+            return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>()};
+        if constexpr (KW == 7 && S == 1) {
+            if (c_out == 32)
+                return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>()};
+        }
+        return {};
+    }
 }
 
 template <typename P, int KC>
-ConvCfg pick_shape_lowp(int kw, int s, int c_out) {
-    if (kw == 7 && s == 1) return pick_lowp<P, 7, 1, KC>(c_out);
-    if (kw == 7 && s == 2) return c_out >= 64 ? pick_lowp<P, 7, 2, KC>(c_out) : ConvCfg{};
-    if (kw == 1 && s == 2) return c_out >= 64 ? pick_lowp<P, 1, 2, KC>(c_out) : ConvCfg{};
+Cands cands_shape_lowp(int kw, int s, int c_out) {
+    if (kw == 7 && s == 1) return cands_lowp<P, 7, 1, KC>(c_out);
+    if (kw == 7 && s == 2) return c_out >= 64 ? cands_lowp<P, 7, 2, KC>(c_out) : Cands{};
+    if (kw == 1 && s == 2) return c_out >= 64 ? cands_lowp<P, 1, 2, KC>(c_out) : Cands{};
     return {};
 }
 
-ConvCfg pick_conv(af_precision p, int kw, int s, int c_in, int c_out) {
+Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
     if (p == AF_F32) {
         if (c_in % 16 != 0) return {};
-        if (kw == 7 && s == 1) return pick_f32<7, 1>(c_out);
-        if (kw == 7 && s == 2) return c_out >= 64 ? pick_f32<7, 2>(c_out) : ConvCfg{};
-        if (kw == 1 && s == 2) return c_out >= 64 ? pick_f32<1, 2>(c_out) : ConvCfg{};
+        if (kw == 7 && s == 1) return cands_f32<7, 1>(c_out);
+        if (kw == 7 && s == 2) return c_out >= 64 ? cands_f32<7, 2>(c_out) : Cands{};
+        if (kw == 1 && s == 2) return c_out >= 64 ? cands_f32<1, 2>(c_out) : Cands{};
         return {};
     }
     const bool kc32 = c_in % 32 == 0;
     if (kw == 1 && !kc32) return {};  // a 1x1 chunk must fill a whole 32-deep MFMA
     if (!kc32 && c_in % 16 != 0) return {};
-    if (p == AF_BF16) return kc32 ? pick_shape_lowp<PBF16, 32>(kw, s, c_out) : pick_shape_lowp<PBF16, 16>(kw, s, c_out);
-    return kc32 ? pick_shape_lowp<PFP8, 32>(kw, s, c_out) : pick_shape_lowp<PFP8, 16>(kw, s, c_out);
+    if (p == AF_BF16) {
+        if (kc32) return cands_shape_lowp<PBF16, 32>(kw, s, c_out);
+        return kw == 7 && s == 1 ? cands_lowp<PBF16, 7, 1, 16>(c_out) : Cands{};
+    }
+    // FP8: k7 convs with >= 32-channel inputs on the 128-deep instruction
+    // (a zero tap pads each 32-channel chunk from 224 to 256); 1x1 projections
+    // and 16-channel inputs on the 32-deep one
+    if (kc32 && kw == 7) return cands_shape_lowp<PFP8X, 32>(kw, s, c_out);
+    if (kc32) return kw == 1 && s == 2 && c_out >= 64 ? cands_lowp<PFP8, 1, 2, 32>(c_out) : Cands{};
+    return kw == 7 && s == 1 ? cands_lowp<PFP8, 7, 1, 16>(c_out) : Cands{};
 }
 
 // ---- host rounding onto BF16 / E4M3 grids (round to nearest even) -----------------
@@ -132,10 +163,53 @@ struct ConvOp {
     int in_buf, out_buf, res_buf;  // res_buf < 0: none
     int amax_in, amax_out;         // FP8 slots
     size_t w_off, b_off;           // folded weights [C_out][KW][C_in] / bias offsets
-    size_t img_off;                // weight image offset (elements)
+    Cands cands;                   // tile shapes this layer can run with
+    int cand = 0;                  // index of the one in use
     ConvCfg cfg;
     int wpt, tt, tiles_per_win;
+    void* d_img = nullptr;         // weight image for cfg (device)
 };
+
+// M tiling of a layer for its tile height: several short windows per tile, or
+// several tiles per window.
+void set_tiling(ConvOp& op) {
+    const int MT = op.cfg.MT;
+    if (op.l_out >= MT) {
+        op.wpt = 1; op.tt = MT; op.tiles_per_win = (op.l_out + MT - 1) / MT;
+    } else if (MT % op.l_out == 0 && op.l_out % 16 == 0 && MT / op.l_out <= op.cfg.WMAX) {
+        op.wpt = MT / op.l_out; op.tt = op.l_out; op.tiles_per_win = 1;
+    } else {
+        op.wpt = 1; op.tt = MT; op.tiles_per_win = 1;
+    }
+}
+
+// Weight image of one conv for tile shape cfg: [C_out/NT][C_in/KC][KWP][NT][PB]
+// in storage precision, taps >= KW and pad columns zero, BF16/FP8 rows
+// swizzled; each chunk is the exact LDS image a workgroup copies with direct
+// loads.  wscale: FP8 per-output-channel scales (FP64).
+std::vector<unsigned char> build_image(const ConvOp& op, const ConvCfg& cfg, af_precision prec,
+                                       const std::vector<double>& wfold, const std::vector<double>& wscale) {
+    const size_t esz = prec == AF_F32 ? 4 : (prec == AF_BF16 ? 2 : 1);
+    const int NT = cfg.NT, KC = cfg.KC, KWP = cfg.KWP, PB = cfg.PB;
+    const int KLs = cfg.KL, SWR = cfg.SWR, SWU = KC / cfg.KL;
+    const int n_chunks = op.c_in / KC;
+    std::vector<unsigned char> img((size_t)(op.c_out / NT) * n_chunks * KWP * NT * PB * esz, 0);
+    for (int o = 0; o < op.c_out; ++o) {
+        const int nt = o / NT, n = o % NT;
+        for (int j = 0; j < op.kw; ++j)
+            for (int c = 0; c < op.c_in; ++c) {
+                const int cc = c / KC, ci = c % KC;
+                const int row = j * NT + n;   // row of the chunk's LDS image
+                const int cs = SWR ? (((ci / KLs) ^ ((row / SWR) & (SWU - 1))) * KLs + ci % KLs) : ci;
+                const size_t e = (((size_t)nt * n_chunks + cc) * KWP * NT + row) * PB + cs;
+                const double v = wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
+                if (prec == AF_F32) ((float*)img.data())[e] = (float)v;
+                else if (prec == AF_BF16) ((uint16_t*)img.data())[e] = host_bf16_bits(v);
+                else img[e] = host_e4m3_bits(v / wscale[op.b_off + o]);
+            }
+    }
+    return img;
+}
 
 }  // namespace
 
@@ -150,7 +224,8 @@ struct af_net {
     int last_L, last_C;
     float fc_b;
     std::vector<ConvOp> ops;
-    void* d_w = nullptr;       // conv weights in storage type
+    std::vector<double> wfold;    // folded conv weights, host copy for rebuilding images
+    std::vector<double> wscale;   // FP8 per-output-channel weight scales
     float* d_b = nullptr;      // conv biases
     float* d_ws = nullptr;     // FP8 per-output-channel scales
     float* d_stem = nullptr;   // stem weights [C][in][k] then bias [C]
@@ -186,7 +261,8 @@ void drop_records(af_net* n) {
 void free_net(af_net* n) {
     if (!n) return;
     drop_records(n);
-    if (n->d_w) (void)hipFree(n->d_w);
+    for (ConvOp& op : n->ops)
+        if (op.d_img) (void)hipFree(op.d_img);
     if (n->d_b) (void)hipFree(n->d_b);
     if (n->d_ws) (void)hipFree(n->d_ws);
     if (n->d_stem) (void)hipFree(n->d_stem);
@@ -263,21 +339,15 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         op.amax_out = n_slots++;
         op.w_off = wfold.size();
         op.b_off = bias.size();
-        op.cfg = pick_conv(prec, kw, s, c_in, c_out);
+        op.cands = conv_candidates(prec, kw, s, c_in, c_out);
+        op.cand = 0;
+        op.cfg = op.cands.empty() ? ConvCfg{} : op.cands[0];
         if (!op.cfg.fn) {
             set_error("no conv kernel for kw=%d stride=%d c_in=%d c_out=%d", kw, s, c_in, c_out);
             return false;
         }
         if (!take_conv(c_out, c_in, kw, w, b)) { set_error("params too short"); return false; }
-        // M tiling: several short windows per tile, or several tiles per window
-        const int MT = op.cfg.MT;
-        if (op.l_out >= MT) {
-            op.wpt = 1; op.tt = MT; op.tiles_per_win = (op.l_out + MT - 1) / MT;
-        } else if (MT % op.l_out == 0 && op.l_out % 16 == 0 && MT / op.l_out <= op.cfg.WMAX) {
-            op.wpt = MT / op.l_out; op.tt = op.l_out; op.tiles_per_win = 1;
-        } else {
-            op.wpt = 1; op.tt = MT; op.tiles_per_win = 1;
-        }
+        set_tiling(op);
         wfold.insert(wfold.end(), w.begin(), w.end());
         for (int o = 0; o < c_out; ++o) bias.push_back((float)b[o]);
         net->macs += (int64_t)op.l_out * c_out * c_in * kw;
@@ -324,14 +394,9 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     net->last_C = C;
     net->n_slots = n_slots;
 
-    // ---- weight images in storage precision ------------------------------------------------
-    // per conv: [C_out/NT][C_in/KC][KWP][NT][PB], taps >= KW and pad columns zero:
-    // each chunk is the exact LDS image a workgroup copies with direct loads
-    std::vector<float> wsc;
-    if (prec == AF_FP8) {
-        wsc.assign(bias.size(), 1.f);
-    }
+    // ---- FP8 weight scales and per-layer weight images -------------------------------------
     std::vector<double> wscale_full(bias.size(), 1.0);
+    std::vector<float> wsc(bias.size(), 1.f);
     if (prec == AF_FP8) {
         for (const ConvOp& op : net->ops) {
             const size_t per = (size_t)op.kw * op.c_in;
@@ -345,44 +410,22 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
             }
         }
     }
-    const size_t esz = prec == AF_F32 ? 4 : (prec == AF_BF16 ? 2 : 1);  // bytes per stored weight
-    size_t img_total = 0;
-    for (ConvOp& op : net->ops) {
-        op.img_off = img_total;
-        img_total += (size_t)(op.c_out / op.cfg.NT) * (op.c_in / op.cfg.KC) * op.cfg.KWP * op.cfg.NT * op.cfg.PB;
-    }
-    std::vector<unsigned char> wbytes(img_total * esz, 0);
-    for (const ConvOp& op : net->ops) {
-        const int NT = op.cfg.NT, KC = op.cfg.KC, KWP = op.cfg.KWP, PB = op.cfg.PB;
-        const int KLs = op.cfg.KL, SWR = op.cfg.SWR, SWU = KC / op.cfg.KL;
-        const int n_chunks = op.c_in / KC;
-        for (int o = 0; o < op.c_out; ++o) {
-            const int nt = o / NT, n = o % NT;
-            for (int j = 0; j < op.kw; ++j)
-                for (int c = 0; c < op.c_in; ++c) {
-                    const int cc = c / KC, ci = c % KC;
-                    const int row = j * NT + n;   // row of the chunk's LDS image
-                    const int cs = SWR ? (((ci / KLs) ^ ((row / SWR) & (SWU - 1))) * KLs + ci % KLs) : ci;
-                    const size_t e = op.img_off + (((size_t)nt * n_chunks + cc) * KWP * NT + row) * PB + cs;
-                    const double v = wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
-                    if (prec == AF_F32) {
-                        ((float*)wbytes.data())[e] = (float)v;
-                    } else if (prec == AF_BF16) {
-                        ((uint16_t*)wbytes.data())[e] = host_bf16_bits(v);
-                    } else {
-                        wbytes[e] = host_e4m3_bits(v / wscale_full[op.b_off + o]);
-                    }
-                }
-        }
-    }
-    // element offsets -> byte offsets are applied at launch (w_off counts elements)
     auto upload = [&](void** dst, const void* src, size_t bytes) -> bool {
         if (bytes == 0) return true;
         if (hipMalloc(dst, bytes) != hipSuccess) return false;
         return hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice) == hipSuccess;
     };
-    if (!upload(&net->d_w, wbytes.data(), wbytes.size()) ||
-        !upload((void**)&net->d_b, bias.data(), bias.size() * 4) ||
+    for (ConvOp& op : net->ops) {
+        std::vector<unsigned char> img = build_image(op, op.cfg, prec, wfold, wscale_full);
+        if (!upload(&op.d_img, img.data(), img.size())) {
+            free_net(net);
+            set_error("device allocation/upload of the weights failed");
+            return AF_ENOMEM;
+        }
+    }
+    net->wfold = wfold;
+    net->wscale = wscale_full;
+    if (!upload((void**)&net->d_b, bias.data(), bias.size() * 4) ||
         !upload((void**)&net->d_stem, stem.data(), stem.size() * 4) ||
         !upload((void**)&net->d_fc, fc.data(), fc.size() * 4) ||
         (prec == AF_FP8 && !upload((void**)&net->d_ws, wsc.data(), wsc.size() * 4))) {
@@ -550,7 +593,6 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
     const size_t bb = buf_bytes(net, batch);
     void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
     uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
-    const size_t esz_w = net->prec == AF_F32 ? 4 : (net->prec == AF_BF16 ? 2 : 1);
     const af_net_desc& d = net->desc;
     af_net* mnet = const_cast<af_net*>(net);  // timing records only; the weights stay read-only
     auto t_begin = [&](int layer, int64_t nw) -> bool {
@@ -596,7 +638,7 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             a.in = buf[op.in_buf];
             a.out = buf[op.out_buf];
             a.res = op.res_buf >= 0 ? buf[op.res_buf] : nullptr;
-            a.w = (const char*)net->d_w + op.img_off * esz_w;
+            a.w = op.d_img;
             a.bias = net->d_b + op.b_off;
             a.wscale = net->d_ws ? net->d_ws + op.b_off : nullptr;
             a.amax_in = amax ? amax + (size_t)op.amax_in * batch : nullptr;
@@ -643,29 +685,22 @@ extern "C" size_t af_timeslide_workspace_bytes(const af_net* net, int64_t n_seg,
     return timeslide_table_bytes(n_seg, n_slides) + af_score_workspace_bytes(net, batch);
 }
 
-extern "C" af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
-                                         const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
-                                         const int64_t* shifts, int64_t n_slides, int64_t stride, float* logits,
-                                         void* ws, size_t ws_bytes, af_stream stream) {
-    clear_error();
-    AF_CHECK_ARG(net && y && seg_off && seg_len && shifts, "net, y, seg_off, seg_len and shifts must be non-null");
-    AF_CHECK_ARG(n_ch == net->desc.in_ch, "n_ch %lld does not match the net's %d inputs", (long long)n_ch, net->desc.in_ch);
-    AF_CHECK_ARG(n >= 1 && ld_y >= n && stride >= 1 && n_seg >= 1 && n_slides >= 1,
-                 "need n >= 1, ld_y >= n, stride >= 1, n_seg >= 1, n_slides >= 1");
-    AF_CHECK_ARG(n_seg * n_slides < (1LL << 30), "too many (segment, slide) pairs");
-    int dev = -1;
-    (void)hipGetDevice(&dev);
-    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+namespace {
+// Build the (segment, slide) table; returns the window total or -1 on error.
+int64_t build_table(const af_net* net, const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
+                    const int64_t* shifts, int64_t n_slides, int64_t stride, int64_t n, std::vector<int64_t>& tab) {
     const int64_t window = net->desc.window;
-    std::vector<int64_t> tab((size_t)(n_seg * n_slides) * 4);
+    tab.assign((size_t)(n_seg * n_slides) * 4, 0);
     int64_t tot = 0;
     for (int64_t sg = 0; sg < n_seg; ++sg) {
-        AF_CHECK_ARG(seg_off[sg] >= 0 && seg_len[sg] >= 0 && seg_off[sg] + seg_len[sg] <= n,
-                     "segment %lld [%lld, +%lld) is not inside [0, n)", (long long)sg, (long long)seg_off[sg],
-                     (long long)seg_len[sg]);
+        if (!(seg_off[sg] >= 0 && seg_len[sg] >= 0 && seg_off[sg] + seg_len[sg] <= n)) {
+            set_error("segment %lld [%lld, +%lld) is not inside [0, n)", (long long)sg, (long long)seg_off[sg],
+                      (long long)seg_len[sg]);
+            return -1;
+        }
         const int64_t nw = seg_len[sg] >= window ? (seg_len[sg] - window) / stride + 1 : 0;
         for (int64_t k = 0; k < n_slides; ++k) {
-            AF_CHECK_ARG(shifts[k] >= 0, "shifts must be non-negative");
+            if (shifts[k] < 0) { set_error("shifts must be non-negative"); return -1; }
             int64_t* e = &tab[(size_t)(sg * n_slides + k) * 4];
             e[0] = seg_off[sg];
             e[1] = seg_len[sg];
@@ -674,8 +709,31 @@ extern "C" af_status af_score_timeslides(const af_net* net, const float* y, int6
             tot += nw;
         }
     }
-    AF_CHECK_ARG(logits || tot == 0, "logits must be non-null");
-    if (tot == 0) return AF_OK;
+    return tot;
+}
+
+af_status check_timeslide_args(const af_net* net, int64_t n_ch, int64_t ld_y, int64_t n, int64_t stride,
+                               int64_t n_seg, int64_t n_slides) {
+    AF_CHECK_ARG(n_ch == net->desc.in_ch, "n_ch %lld does not match the net's %d inputs", (long long)n_ch, net->desc.in_ch);
+    AF_CHECK_ARG(n >= 1 && ld_y >= n && stride >= 1 && n_seg >= 1 && n_slides >= 1,
+                 "need n >= 1, ld_y >= n, stride >= 1, n_seg >= 1, n_slides >= 1");
+    AF_CHECK_ARG(n_seg * n_slides < (1LL << 30), "too many (segment, slide) pairs");
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    return AF_OK;
+}
+}  // namespace
+
+extern "C" af_status af_timeslide_prepare(const af_net* net, const int64_t* seg_off, const int64_t* seg_len,
+                                          int64_t n_seg, const int64_t* shifts, int64_t n_slides, int64_t stride,
+                                          int64_t n, void* ws, size_t ws_bytes, af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && seg_off && seg_len && shifts, "net, seg_off, seg_len and shifts must be non-null");
+    af_status st = check_timeslide_args(net, net->desc.in_ch, n, n, stride, n_seg, n_slides);
+    if (st != AF_OK) return st;
+    std::vector<int64_t> tab;
+    if (build_table(net, seg_off, seg_len, n_seg, shifts, n_slides, stride, n, tab) < 0) return AF_EINVAL;
     const size_t tb = timeslide_table_bytes(n_seg, n_slides);
     AF_CHECK_ARG(ws && ws_bytes >= tb + af_score_workspace_bytes(net, 1),
                  "workspace too small: need at least %zu bytes", tb + af_score_workspace_bytes(net, 1));
@@ -683,9 +741,170 @@ extern "C" af_status af_score_timeslides(const af_net* net, const float* y, int6
     // the table is a few KB; a blocking copy keeps its host storage simple
     AF_HIP(hipMemcpyAsync(ws, tab.data(), tab.size() * sizeof(int64_t), hipMemcpyHostToDevice, s));
     AF_HIP(hipStreamSynchronize(s));
+    return AF_OK;
+}
+
+extern "C" af_status af_score_timeslides_prepared(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y,
+                                                  int64_t n, int64_t n_seg, int64_t n_slides, int64_t stride,
+                                                  int64_t n_windows, float* logits, void* ws, size_t ws_bytes,
+                                                  af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && y, "net and y must be non-null");
+    af_status st = check_timeslide_args(net, n_ch, ld_y, n, stride, n_seg, n_slides);
+    if (st != AF_OK) return st;
+    AF_CHECK_ARG(n_windows >= 0 && (logits || n_windows == 0), "bad n_windows or logits");
+    if (n_windows == 0) return AF_OK;
+    const size_t tb = timeslide_table_bytes(n_seg, n_slides);
+    AF_CHECK_ARG(ws && ws_bytes >= tb + af_score_workspace_bytes(net, 1),
+                 "workspace too small: need at least %zu bytes", tb + af_score_workspace_bytes(net, 1));
     int64_t zero[4] = {0, 0, 0, 0};
-    return score_batches(net, y, ld_y, n, stride, tot, zero, 0, (const int64_t*)ws, (int)(n_seg * n_slides), logits,
-                         (char*)ws + tb, ws_bytes - tb, s);
+    return score_batches(net, y, ld_y, n, stride, n_windows, zero, 0, (const int64_t*)ws, (int)(n_seg * n_slides),
+                         logits, (char*)ws + tb, ws_bytes - tb, (hipStream_t)stream);
+}
+
+extern "C" af_status af_score_timeslides(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                                         const int64_t* seg_off, const int64_t* seg_len, int64_t n_seg,
+                                         const int64_t* shifts, int64_t n_slides, int64_t stride, float* logits,
+                                         void* ws, size_t ws_bytes, af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && y && seg_off && seg_len && shifts, "net, y, seg_off, seg_len and shifts must be non-null");
+    af_status st = check_timeslide_args(net, n_ch, ld_y, n, stride, n_seg, n_slides);
+    if (st != AF_OK) return st;
+    std::vector<int64_t> tab;
+    const int64_t tot = build_table(net, seg_off, seg_len, n_seg, shifts, n_slides, stride, n, tab);
+    if (tot < 0) return AF_EINVAL;
+    AF_CHECK_ARG(logits || tot == 0, "logits must be non-null");
+    if (tot == 0) return AF_OK;
+    st = af_timeslide_prepare(net, seg_off, seg_len, n_seg, shifts, n_slides, stride, n, ws, ws_bytes, stream);
+    if (st != AF_OK) return st;
+    return af_score_timeslides_prepared(net, y, n_ch, ld_y, n, n_seg, n_slides, stride, tot, logits, ws, ws_bytes,
+                                        stream);
+}
+
+namespace afm {
+int net_window(const af_net* net) { return net->desc.window; }
+int net_in_ch(const af_net* net) { return net->desc.in_ch; }
+int net_device(const af_net* net) { return net->device; }
+
+af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
+                      int64_t n_windows, const int64_t* table, int n_entries, float* logits, void* ws,
+                      size_t ws_bytes, hipStream_t s) {
+    int64_t zero[4] = {0, 0, 0, 0};
+    if (n_windows == 0) return AF_OK;
+    return score_batches(net, y, ld_y, n, stride, n_windows, zero, 0, table, n_entries, logits, ws, ws_bytes, s);
+}
+}  // namespace afm
+
+extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_t ws_bytes, af_stream stream,
+                                     int64_t* n_changed) {
+    clear_error();
+    AF_CHECK_ARG(net && ws, "net and ws must be non-null");
+    AF_CHECK_ARG(batch >= 1 && batch < (1LL << 24) && batch * net->act_elems < (1LL << 31), "bad batch size");
+    AF_CHECK_ARG(ws_bytes >= af_score_workspace_bytes(net, batch), "workspace too small for batch %lld",
+                 (long long)batch);
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+    const size_t bb = buf_bytes(net, batch);
+    void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
+    uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
+    // defined contents: activations zero, FP8 maxima 1.0
+    const int64_t words = (int64_t)(3 * bb / 4);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)ws, words, 0u);
+    if (amax) {
+        const int64_t cnt = (int64_t)net->n_slots * batch;
+        hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, s, amax, cnt, 0x3F800000u);
+    }
+    AF_LAUNCHED();
+    hipEvent_t e0, e1;
+    AF_HIP(hipEventCreate(&e0));
+    AF_HIP(hipEventCreate(&e1));
+    int64_t changed = 0;
+    af_status result = AF_OK;
+    for (ConvOp& op : net->ops) {
+        if (op.cands.size() < 2) continue;
+        int best = op.cand;
+        float best_ms = 1e30f;
+        for (int ci = 0; ci < (int)op.cands.size() && result == AF_OK; ++ci) {
+            ConvOp trial = op;
+            trial.cfg = op.cands[ci];
+            set_tiling(trial);
+            std::vector<unsigned char> img = build_image(trial, trial.cfg, net->prec, net->wfold, net->wscale);
+            void* d_img = nullptr;
+            if (hipMalloc(&d_img, img.size()) != hipSuccess ||
+                hipMemcpy(d_img, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                if (d_img) (void)hipFree(d_img);
+                set_error("autotune: weight image upload failed");
+                result = AF_ENOMEM;
+                break;
+            }
+            ConvArgs a{};
+            a.in = buf[op.in_buf];
+            a.out = buf[op.out_buf];
+            a.res = op.res_buf >= 0 ? buf[op.res_buf] : nullptr;
+            a.w = d_img;
+            a.bias = net->d_b + op.b_off;
+            a.wscale = net->d_ws ? net->d_ws + op.b_off : nullptr;
+            a.amax_in = amax ? amax + (size_t)op.amax_in * batch : nullptr;
+            a.amax_out = nullptr;   // keep the maxima at 1.0 while timing
+            a.C_in = op.c_in; a.C_out = op.c_out; a.L_in = op.l_in; a.L_out = op.l_out;
+            a.relu = op.relu; a.n_win = (int)batch;
+            a.wpt = trial.wpt; a.tt = trial.tt; a.tiles_per_win = trial.tiles_per_win;
+            trial.cfg.fn(a, s);   // warm-up
+            (void)hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3; ++rep) trial.cfg.fn(a, s);
+            (void)hipEventRecord(e1, s);
+            hipError_t err = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            (void)hipFree(d_img);
+            if (err != hipSuccess) {
+                set_error("autotune: timing failed: %s", hipGetErrorString(err));
+                result = AF_EHIP;
+                break;
+            }
+            if (ms < best_ms) { best_ms = ms; best = ci; }
+        }
+        if (result != AF_OK) break;
+        if (best != op.cand) {
+            ConvOp next = op;
+            next.cand = best;
+            next.cfg = op.cands[best];
+            set_tiling(next);
+            std::vector<unsigned char> img = build_image(next, next.cfg, net->prec, net->wfold, net->wscale);
+            void* d_img = nullptr;
+            if (hipMalloc(&d_img, img.size()) != hipSuccess ||
+                hipMemcpy(d_img, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+                if (d_img) (void)hipFree(d_img);
+                set_error("autotune: weight image upload failed");
+                result = AF_ENOMEM;
+                break;
+            }
+            (void)hipFree(op.d_img);
+            next.d_img = d_img;
+            op = next;
+            ++changed;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (n_changed) *n_changed = changed;
+    return result;
+}
+
+extern "C" af_status af_net_layer_tile(const af_net* net, int64_t layer, int32_t* mt, int32_t* nt,
+                                       int32_t* n_candidates, int32_t* chosen) {
+    clear_error();
+    AF_CHECK_ARG(net && mt && nt && n_candidates && chosen, "bad arguments");
+    AF_CHECK_ARG(layer >= 1 && layer <= (int64_t)net->ops.size(), "layer must be a conv index in [1, %zu]",
+                 net->ops.size());
+    const ConvOp& op = net->ops[layer - 1];
+    *mt = op.cfg.MT;
+    *nt = op.cfg.NT;
+    *n_candidates = (int32_t)op.cands.size();
+    *chosen = op.cand;
+    return AF_OK;
 }
 
 extern "C" int64_t af_net_n_layers(const af_net* net) { return net ? (int64_t)net->layer_macs.size() : 0; }

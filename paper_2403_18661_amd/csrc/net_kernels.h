@@ -59,6 +59,14 @@ struct PFP8 {
     static constexpr int KL = 8;
     static constexpr bool kFP8 = true;
 };
+// FP8 on the 16x16x128 matrix instruction (32 k values per lane, unit block
+// scales): twice the FP8 rate of the 16x16x32 form
+struct PFP8X {
+    using Act = uint16_t;
+    using Op = uint8_t;
+    static constexpr int KL = 32;
+    static constexpr bool kFP8 = true;
+};
 
 template <typename P>
 __device__ __forceinline__ float act_to_f32(typename P::Act v) {
@@ -75,6 +83,15 @@ template <typename P>
 __device__ __forceinline__ void mfma_step(f4v& acc, const typename P::Op* a, const typename P::Op* b) {
     if constexpr (sizeof(typename P::Op) == 4) {
         acc = __builtin_amdgcn_mfma_f32_16x16x4f32(*(const float*)a, *(const float*)b, acc, 0, 0, 0);
+    } else if constexpr (P::kFP8 && P::KL == 32) {
+        typedef int i32x8 __attribute__((ext_vector_type(8)));
+        // two 16-byte LDS reads per operand (rows are 16-byte aligned)
+        const uint4 a0 = ((const uint4*)a)[0], a1 = ((const uint4*)a)[1];
+        const uint4 b0 = ((const uint4*)b)[0], b1 = ((const uint4*)b)[1];
+        const i32x8 av = {(int)a0.x, (int)a0.y, (int)a0.z, (int)a0.w, (int)a1.x, (int)a1.y, (int)a1.z, (int)a1.w};
+        const i32x8 bv = {(int)b0.x, (int)b0.y, (int)b0.z, (int)b0.w, (int)b1.x, (int)b1.y, (int)b1.z, (int)b1.w};
+        // formats 0/0 = E4M3 x E4M3; block scales 127 = 2^0
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(av, bv, acc, 0, 0, 0, 127, 0, 127);
     } else if constexpr (P::kFP8) {
         long av = *(const long*)a, bv = *(const long*)b;
         acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
@@ -140,7 +157,8 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     static_assert(KC % KL == 0, "lane k-run must stay inside one tap");
     constexpr int OPB = (int)sizeof(Op);
     constexpr int PA = KC + 16 / OPB;           // slab row pitch in elements (16 B of padding)
-    constexpr int PB = OPB == 4 ? KC + 4 : KC;  // weight row pitch (FP32 lanes read 4 B: pad)
+    // weight row pitch: FP32 lanes read 4 B (pad 4); 32-byte FP8 lane reads (pad 16 B)
+    constexpr int PB = OPB == 4 ? KC + 4 : (KL == 32 ? KC + 16 : KC);
     // BF16/FP8 weight rows are not padded; instead the KL-element units of row
     // r are XOR-swizzled by (r / SWR) & (KC/KL - 1), so that the 16 rows one
     // MFMA operand read touches fall in distinct LDS banks

@@ -16,6 +16,7 @@
 // FFT, and keep the 8192 - 2(M-1) samples the circular wrap does not touch.
 // Blocks never straddle a PSD hop, so every output uses its own hop's filter.
 #include "fft_lds.h"
+#include "internal.h"
 
 namespace afm {
 
@@ -178,6 +179,47 @@ extern "C" size_t af_whiten_workspace_bytes(int64_t n_ch, int64_t nperseg, int64
     return resp_bytes(n_ch, n_psd);
 }
 
+namespace afm {
+// Filter responses for n_psd PSDs (FP64 build, FP32 result) into resp
+// [n_psd][n_ch][WB_N/2+1].  Arguments are assumed validated.
+af_status whiten_build_response(const double* psd, int64_t n_ch, int64_t n_psd, int64_t nperseg, double fs,
+                                double highpass, int M, float* resp, hipStream_t s) {
+    const double* twL = twiddles_f64((int)nperseg);
+    const double* twB = twiddles_f64(WB_N);
+    if (!twL || !twB) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
+    const double out_scale = sqrt(2.0 / fs) / (double)WB_N;
+    hipError_t e = nperseg == 4096 ? launch_fir<12>(psd, n_ch, n_psd, fs, highpass, M, twL, twB, out_scale, resp, s)
+                                   : launch_fir<11>(psd, n_ch, n_psd, fs, highpass, M, twL, twB, out_scale, resp, s);
+    if (e != hipSuccess) { set_error("whitening filter launch failed: %s", hipGetErrorString(e)); return AF_EHIP; }
+    return AF_OK;
+}
+
+// Overlap-save application of precomputed responses (see af_whiten).
+af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
+                       const float* resp, int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out,
+                       float* y, int64_t ld_y, hipStream_t s) {
+    const float* twF = twiddles_f32(WB_N);
+    if (!twF) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
+    const int V = WB_N - 2 * (M - 1);
+    if (n_psd <= 1) psd_hop = n_out;
+    const int64_t bph = (psd_hop + V - 1) / V;
+    const int64_t last_len = n_out - (n_psd - 1) * psd_hop;
+    const int64_t n_blocks = (n_psd - 1) * bph + (last_len + V - 1) / V;
+    AF_CHECK_ARG(n_blocks < (1LL << 31), "too many whitening blocks");
+    dim3 grid((unsigned)n_blocks, (unsigned)((n_ch + 1) / 2));
+    if (xt == AF_IN_F64)
+        hipLaunchKernelGGL((whiten_block_kernel<256, double>), grid, dim3(256), 0, s, (const double*)x, n_ch, n, ld_x,
+                           (float)prescale, prescale, resp, n_psd, psd_hop, bph, M, out_start, n_out,
+                           (const cpx<float>*)twF, y, ld_y);
+    else
+        hipLaunchKernelGGL((whiten_block_kernel<256, float>), grid, dim3(256), 0, s, (const float*)x, n_ch, n, ld_x,
+                           (float)prescale, prescale, resp, n_psd, psd_hop, bph, M, out_start, n_out,
+                           (const cpx<float>*)twF, y, ld_y);
+    AF_LAUNCHED();
+    return AF_OK;
+}
+}  // namespace afm
+
 extern "C" af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x,
                                double fs, double prescale, const double* psd, int64_t nperseg,
                                int64_t n_psd, int64_t psd_hop, double fduration, double highpass,
@@ -198,39 +240,15 @@ extern "C" af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t
     AF_CHECK_ARG(out_start >= M && out_start + n_out + M <= n,
                  "output range [%lld, %lld) needs %d samples of context on each side within n = %lld",
                  (long long)out_start, (long long)(out_start + n_out), M, (long long)n);
-    const int V = WB_N - 2 * (M - 1);
-    AF_CHECK_ARG(V > 0, "filter too long for the %d-point whitening block", WB_N);
+    AF_CHECK_ARG(WB_N - 2 * (M - 1) > 0, "filter too long for the %d-point whitening block", WB_N);
     if (n_psd > 1)
         AF_CHECK_ARG(psd_hop >= 1 && (n_psd - 1) * psd_hop < n_out,
                      "psd_hop must be >= 1 and every PSD hop must start inside the output");
-    else
-        psd_hop = n_out;
     const size_t need = resp_bytes(n_ch, n_psd);
     AF_CHECK_ARG(ws && ws_bytes >= need, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
-    const double* twL = twiddles_f64((int)nperseg);
-    const double* twB = twiddles_f64(WB_N);
-    const float* twF = twiddles_f32(WB_N);
-    if (!twL || !twB || !twF) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
     hipStream_t s = (hipStream_t)stream;
     float* resp = (float*)ws;
-    const double out_scale = sqrt(2.0 / fs) / (double)WB_N;
-    hipError_t e = nperseg == 4096
-                       ? launch_fir<12>(psd, n_ch, n_psd, fs, highpass, M, twL, twB, out_scale, resp, s)
-                       : launch_fir<11>(psd, n_ch, n_psd, fs, highpass, M, twL, twB, out_scale, resp, s);
-    if (e != hipSuccess) { set_error("whitening filter launch failed: %s", hipGetErrorString(e)); return AF_EHIP; }
-    const int64_t bph = (psd_hop + V - 1) / V;
-    const int64_t last_len = n_out - (n_psd - 1) * psd_hop;
-    const int64_t n_blocks = (n_psd - 1) * bph + (last_len + V - 1) / V;
-    AF_CHECK_ARG(n_blocks < (1LL << 31), "too many whitening blocks");
-    dim3 grid((unsigned)n_blocks, (unsigned)((n_ch + 1) / 2));
-    if (xt == AF_IN_F64)
-        hipLaunchKernelGGL((whiten_block_kernel<256, double>), grid, dim3(256), 0, s, (const double*)x, n_ch, n, ld_x,
-                           (float)prescale, prescale, resp, n_psd, psd_hop, bph, M, out_start, n_out,
-                           (const cpx<float>*)twF, y, ld_y);
-    else
-        hipLaunchKernelGGL((whiten_block_kernel<256, float>), grid, dim3(256), 0, s, (const float*)x, n_ch, n, ld_x,
-                           (float)prescale, prescale, resp, n_psd, psd_hop, bph, M, out_start, n_out,
-                           (const cpx<float>*)twF, y, ld_y);
-    AF_LAUNCHED();
-    return AF_OK;
+    af_status st = whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, resp, s);
+    if (st != AF_OK) return st;
+    return whiten_apply(x, xt, n_ch, n, ld_x, prescale, resp, n_psd, psd_hop, M, out_start, n_out, y, ld_y, s);
 }

@@ -145,3 +145,20 @@ def test_fused_unavailable_for_fp32():
     assert not net.fused
     with pytest.raises(P.AframeError, match="EINVAL"):
         net.fused = True
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_autotune_keeps_logits(prec):
+    # switching tile shapes leaves every window's arithmetic unchanged
+    P = need_gpu()
+    banner(f"autotune resnet {prec}")
+    params = make_params(RESNET_ARCH, seed=23)
+    y = dev(series(3072 + 128 * 15, seed=24))
+    net = P.Net(RESNET_ARCH, params, prec)
+    before = net.score_windows(y, 128).cpu().numpy()
+    changed = net.autotune(batch=64)
+    tiles = net.tiles()
+    assert len(tiles) == 36 and all(0 <= t[3] < t[2] for t in tiles if t[2] > 0)
+    after = net.score_windows(y, 128).cpu().numpy()
+    print(f"autotune changed {changed} layers")
+    np.testing.assert_allclose(after, before, atol=1e-5 if prec == "f32" else 2e-3)

@@ -55,3 +55,25 @@ def test_rejects_segment_outside_series():
     y = dev(np.zeros((2, 5000), np.float32))
     with pytest.raises(P.AframeError, match="EINVAL"):
         P.score_timeslides(net, y, [1000], [4500], [2048])
+
+
+def test_prepared_graph_replays_match_direct_call():
+    # the captured graph, replayed several times with eager work in between,
+    # gives the direct call's logits every time
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.timeslides import TimeslidePlan
+    banner("timeslide graph replay")
+    params = make_params(TINY_ARCH, seed=15)
+    y = dev(np.random.default_rng(16).standard_normal((2, 20000)).astype(np.float32))
+    net = P.Net(TINY_ARCH, params, "bf16")
+    seg_off, seg_len, shifts = [0, 9000], [9000, 11000], [2048 * k for k in range(1, 6)]
+    direct = P.score_timeslides(net, y, seg_off, seg_len, shifts, stride=1024).cpu().numpy()
+    plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=1024, graph=True)
+    for rep in range(3):
+        plan.logits.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run()
+        plan.stream.synchronize()
+        np.testing.assert_array_equal(plan.logits[:plan.n_windows].cpu().numpy(), direct)
+        _ = (y * 2).sum().item()          # unrelated eager work between replays
