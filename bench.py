@@ -145,6 +145,7 @@ def main():
     ap.add_argument("--batch", type=int, default=8192)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timeslide", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
@@ -175,6 +176,9 @@ def main():
     for prec in args.precisions.split(","):
         net = P.Net(arch, params, prec)
         path = OfflinePath(net, x.shape[1], cfg, batch=args.batch)
+        if not args.no_autotune:
+            changed = net.autotune(batch=min(args.batch, 2048), ws=path.ws_net)
+            log(f"{prec}: autotune switched {changed} of {net.n_layers - 2} conv layers")
         for _ in range(args.warmup):
             path.run(xd)
         torch.cuda.synchronize()
@@ -213,7 +217,7 @@ def main():
                      "frac": conv_flop / conv_ms * 1e-9 / PEAK_TFLOPS[prec]},
             "whiten_gbs": wh_bytes / (stage_ms[1] * 1e-3) * 1e-9,
             "layers": {"ms": prof["ms"].tolist(), "flops": prof["flops"].tolist(),
-                       "launches": prof["launches"].tolist()},
+                       "launches": prof["launches"].tolist(), "tiles": net.tiles()},
         }
         integ[prec] = path.integrated.cpu().numpy().astype(np.float64)
         log(f"{prec}: {res[prec]['value']:.0f} windows/s, {ms_step:.1f} ms/step, conv "

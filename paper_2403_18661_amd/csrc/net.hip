@@ -85,9 +85,11 @@ Cands cands_lowp(int c_out) {
     } else {
         constexpr bool DB_WIDE = !(KW == 7 && S == 2);
         if (c_out % 128 == 0)
-            return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>()};
+            return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
+                    make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>()};
         if (c_out == 64)
-            return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>()};
+            return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
+                    make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>()};
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>()};

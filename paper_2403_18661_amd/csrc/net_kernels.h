@@ -101,6 +101,34 @@ __device__ __forceinline__ void mfma_step(f4v& acc, const typename P::Op* a, con
     }
 }
 
+// Same product with the A operand already in registers (D dwords per lane).
+template <typename P, int D>
+__device__ __forceinline__ void mfma_regs(f4v& acc, const uint32_t (&a)[D], const typename P::Op* b) {
+    if constexpr (P::kFP8) {
+        static_assert(D == 2, "FP8 16x16x32 operands are 8 bytes per lane");
+        const long av = (long)(((uint64_t)a[1] << 32) | a[0]);
+        const long bv = *(const long*)b;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(av, bv, acc, 0, 0, 0);
+    } else {
+        static_assert(D == 4, "BF16 16x16x32 operands are 16 bytes per lane");
+        const uint4 w = make_uint4(a[0], a[1], a[2], a[3]);
+        const bf16x8 av = __builtin_bit_cast(bf16x8, w);
+        const bf16x8 bv = *(const bf16x8*)b;
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+}
+
+template <int D, typename T>
+__device__ __forceinline__ void load_words(uint32_t (&w)[D], const T* p) {
+    if constexpr (D == 4) {
+        const uint4 v = *(const uint4*)p;
+        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+    } else {
+        const uint2 v = *(const uint2*)p;
+        w[0] = v.x; w[1] = v.y;
+    }
+}
+
 struct ConvArgs {
     const void* in;        // [B][L_in][C_in]  (P::Act)
     void* out;             // [B][L_out][C_out] (P::Act)
@@ -164,6 +192,8 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     // MFMA operand read touches fall in distinct LDS banks
     constexpr int SWU = KC / KL;                                    // units per row
     constexpr int SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
+    // tap-shift reuse of the A operand (see the k-loop)
+    constexpr bool SHIFT = S == 1 && KW > 1 && MK == KC && KPAD == KW * KC && OPB <= 2 && KL == 8;
     constexpr int PAD = (KW - 1) / 2;
     // rows of all windows' slabs: wpt windows need (MT - wpt) S + wpt KWP rows,
     // largest at wpt = WMAX when KWP >= S and at wpt = 1 otherwise (1x1, stride 2)
@@ -304,6 +334,45 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
         }
         const Op* slab = smem + buf * (SLAB_EL + W_EL);
         const Op* wl = slab + SLAB_EL;
+        if constexpr (SHIFT) {
+            // stride 1, one tap per k-step: the A operand of tap j+1 is the one
+            // of tap j moved up one row.  Rotate it left by one lane within each
+            // 16-lane row (DPP row_ror:15) and let lane 15 of every row read
+            // the one new slab row from LDS (4 active lanes per tile).
+            constexpr int D = KL * OPB / 4;
+            uint32_t af[TM][D];
+#pragma unroll
+            for (int i = 0; i < TM; ++i) load_words<D>(af[i], slab + arow[i] + g * KL);
+#pragma unroll
+            for (int j = 0; j < KW; ++j) {
+                const int c = g * KL;
+                const Op* bb[TN];
+#pragma unroll
+                for (int jn = 0; jn < TN; ++jn) {
+                    const int row = j * NT + (wn * TN + jn) * 16 + r16;
+                    const int cs = SWR ? (((c / KL) ^ ((row / (SWR ? SWR : 1)) & (SWU - 1))) * KL) : c;
+                    bb[jn] = wl + row * PB + cs;
+                }
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int jn = 0; jn < TN; ++jn) mfma_regs<P, D>(acc[i][jn], af[i], bb[jn]);
+                if (j + 1 < KW) {
+#pragma unroll
+                    for (int i = 0; i < TM; ++i) {
+                        uint32_t ex[D];
+#pragma unroll
+                        for (int d = 0; d < D; ++d) ex[d] = 0u;
+                        if (r16 == 15) load_words<D>(ex, slab + arow[i] + (j + 1) * PA + g * KL);
+#pragma unroll
+                        for (int d = 0; d < D; ++d) {
+                            const uint32_t rot = (uint32_t)__builtin_amdgcn_update_dpp(0, (int)af[i][d], 0x12F, 0xF, 0xF, false);
+                            af[i][d] = r16 == 15 ? ex[d] : rot;
+                        }
+                    }
+                }
+            }
+        } else
 #pragma unroll
         for (int ks = 0; ks < KPAD; ks += MK) {
             const int k = ks + g * KL;

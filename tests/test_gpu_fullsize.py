@@ -1,0 +1,74 @@
+"""GPU parity at full size: the 1 h workload in the benchmark's launch
+configuration, checked on sampled outputs that the FP64 oracle recomputes one
+by one (PSD of sampled hops, whitened samples of sampled windows, logits of
+those windows, one integrated value)."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import RESNET_ARCH, make_params
+from synth.workloads import PSD_LEN, hour_strain
+from tests.gpu_util import banner, need_gpu, rel_l2
+
+pytestmark = pytest.mark.gpu
+FS = 2048.0
+HOP, M, WIN, STRIDE = 16384, 1024, 3072, 128
+
+
+@pytest.fixture(scope="module")
+def hour_run():
+    P = need_gpu()
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    banner("full-size hour workload, FP32")
+    x, _ = hour_strain(seed=0)
+    params = make_params(RESNET_ARCH, seed=0)
+    net = P.Net(RESNET_ARCH, params, "f32")
+    path = OfflinePath(net, x.shape[1], PathConfig(psd_len=PSD_LEN), batch=8192)
+    path.run(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    return {"x": x, "params": params, "psd": path.psd.cpu().numpy(), "y": path.y.cpu().numpy(),
+            "logits": path.logits.cpu().numpy(), "integ": path.integrated.cpu().numpy(), "n_windows": path.n_windows}
+
+
+def oracle_window(x, params, k):
+    """Oracle whitened span and logit of window k of the hour workload."""
+    n0 = PSD_LEN + M
+    lo, hi = k * STRIDE, k * STRIDE + WIN
+    y = np.empty((2, WIN))
+    for j in range(lo // HOP, (hi - 1) // HOP + 1):
+        a, b = max(lo, j * HOP), min(hi, (j + 1) * HOP)
+        psd = oracle.welch_psd(x[:, j * HOP: j * HOP + PSD_LEN], FS)
+        taps = oracle.whitening_fir(psd, FS)
+        for c in range(2):
+            y[c, a - lo:b - lo] = oracle.whiten_at(x[c], taps[c], np.arange(n0 + a, n0 + b), FS)
+    return y, oracle.net_forward(params, RESNET_ARCH, y[None])[0]
+
+
+def test_counts(hour_run):
+    assert hour_run["n_windows"] == 57600
+    assert hour_run["y"].shape == (2, 57599 * STRIDE + WIN)
+    assert hour_run["psd"].shape == (451, 2, 2049)
+    assert hour_run["integ"].shape == (57585,)
+
+
+@pytest.mark.parametrize("j", [0, 1, 225, 450])
+def test_sampled_psd(hour_run, j):
+    x = hour_run["x"]
+    ref = oracle.welch_psd(x[:, j * HOP: j * HOP + PSD_LEN] * 1e21, FS)
+    np.testing.assert_allclose(hour_run["psd"][j], ref, rtol=1e-10)
+
+
+@pytest.mark.parametrize("k", [0, 127, 20000, 45311, 57599])
+def test_sampled_windows(hour_run, k):
+    y_ref, logit_ref = oracle_window(hour_run["x"], hour_run["params"], k)
+    y = hour_run["y"][:, k * STRIDE: k * STRIDE + WIN]
+    for c in range(2):
+        assert rel_l2(y[c], y_ref[c]) < 1e-5
+    assert abs(hour_run["logits"][k] - logit_ref) < 1e-3
+
+
+def test_sampled_integrated(hour_run):
+    i = 31000
+    refs = [oracle_window(hour_run["x"], hour_run["params"], k)[1] for k in range(i, i + 16)]
+    assert abs(hour_run["integ"][i] - oracle.integrate(np.array(refs), 16)[0]) < 1e-3

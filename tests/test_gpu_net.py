@@ -6,6 +6,7 @@ import torch
 
 import oracle
 from synth import RESNET_ARCH, TINY_ARCH, make_params
+from synth.params import NetArch
 from tests.gpu_util import banner, dev, need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -162,3 +163,24 @@ def test_autotune_keeps_logits(prec):
     after = net.score_windows(y, 128).cpu().numpy()
     print(f"autotune changed {changed} layers")
     np.testing.assert_allclose(after, before, atol=1e-5 if prec == "f32" else 2e-3)
+
+
+SHALLOW = [NetArch("shallow32", 2, 32, 7, 2, True, (32,), (1,)),
+           NetArch("shallow64", 2, 32, 7, 2, True, (32, 64), (1, 1)),
+           NetArch("shallow128", 2, 32, 7, 2, True, (32, 64, 128), (1, 1, 1))]
+
+
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("fp8", 2e-3)])
+@pytest.mark.parametrize("arch", SHALLOW, ids=lambda a: a.name)
+def test_shallow_resnets_vs_emulation(arch, prec, tol):
+    # every low-precision layer kind (stride-1 k7 with the tap-shift operand
+    # reuse, stride-2 k7, 1x1 projection, 32/64/128 wide) against the
+    # quantisation-emulating oracle on nets shallow enough for it to pin tightly
+    P = need_gpu()
+    banner(f"shallow {arch.name} {prec}")
+    params = make_params(arch, seed=25)
+    y = series(3072 + 128 * 7, seed=26)
+    got = P.Net(arch, params, prec).score_windows(dev(y), 128).cpu().numpy()
+    emu = oracle_logits(params, arch, y, 128, len(got), precision=prec)
+    print(f"{arch.name} {prec}: max|d| vs emulation {np.abs(got - emu).max():.2e}")
+    assert np.abs(got - emu).max() < tol
