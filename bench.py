@@ -146,6 +146,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-timeslide", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--layers-out", default=None, help="write per-layer timings and tiles to this JSON file")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
@@ -225,6 +226,9 @@ def main():
         del path, net
         torch.cuda.empty_cache()
 
+    if args.layers_out:
+        with open(args.layers_out, "w") as f:
+            json.dump({p: r["layers"] for p, r in res.items()}, f)
     import scipy.stats
     head = "f32" if "f32" in res else list(res)[0]
     precisions = {}
@@ -248,7 +252,7 @@ def main():
                                "whitening with 32 Hz high-pass, 57,600 windows of 2x3072 at 16 Hz, ResNet-1D "
                                "[3,4,6,3] x (32,64,128,256) k7 folded BN, 1 s integration",
                    "windows_per_step": int(args.windows), "batch": args.batch, "injections": len(inj)},
-        "roofline": {"bound": "mfma", "kernel": "conv_mfma_kernel (all 36 conv launches of a batch)",
+        "roofline": {"bound": "mfma", "kernel": "conv_mfma_kernel (all 35 MFMA conv launches of a batch)",
                      "achieved": h["conv"]["tflops"], "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
                      "frac": h["conv"]["frac"], "traffic": None,
                      "avg_launch_ms": h["conv"]["ms_per_step"] / max(n_launch, 1),

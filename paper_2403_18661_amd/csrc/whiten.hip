@@ -108,10 +108,13 @@ __global__ void __launch_bounds__(NT) whiten_block_kernel(
     const TX* x0 = x + c0 * ld_x;
     const TX* x1 = x + (c0 + 1) * ld_x;
     const int64_t in0 = out_start + o0 - (M - 1);
+    // only the inputs the block's outputs depend on: the FFT's rounding then
+    // depends on nothing else (streamed and batch blocks agree bit for bit)
+    const int64_t in_len = (o_end - o0) + 2 * (M - 1);
     for (int t = threadIdx.x; t < WB_N; t += NT) {
         const int64_t p = in0 + t;
         float v0 = 0.f, v1 = 0.f;
-        if (p < n) {
+        if (t < in_len && p < n) {
             if constexpr (sizeof(TX) == 8) {
                 v0 = (float)((double)x0[p] * prescale_d);
                 if (has1) v1 = (float)((double)x1[p] * prescale_d);

@@ -122,9 +122,11 @@ def run_realtime(server, data, seconds, fs=2048, chunk_s=1.0, prefill_s=66.0, se
         for a in range(0, n_pre, n_chunk):
             server.push(i, data[i][:, a:a + n_chunk])
         pos[i] = n_pre
-    while server.tick() > 0 or any(server.poll(i)[1].size for i in range(S)):
-        pass
-    server.tick()
+    # a tick consumes at most max_tick samples per stream: drain the pre-fill
+    for _ in range(int(prefill_s * fs) // int(server.cfg.max_tick) + 3):
+        server.tick()
+        for i in range(S):
+            server.poll(i)
     server.stats(reset=True)
     t0 = time.perf_counter()
     nxt = [t0 + rng.exponential(chunk_s) for _ in range(S)]

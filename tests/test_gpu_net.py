@@ -159,7 +159,7 @@ def test_autotune_keeps_logits(prec):
     before = net.score_windows(y, 128).cpu().numpy()
     changed = net.autotune(batch=64)
     tiles = net.tiles()
-    assert len(tiles) == 36 and all(0 <= t[3] < t[2] for t in tiles if t[2] > 0)
+    assert len(tiles) == 35 and all(0 <= t[3] < t[2] for t in tiles if t[2] > 0)
     after = net.score_windows(y, 128).cpu().numpy()
     print(f"autotune changed {changed} layers")
     np.testing.assert_allclose(after, before, atol=1e-5 if prec == "f32" else 2e-3)
@@ -170,7 +170,7 @@ SHALLOW = [NetArch("shallow32", 2, 32, 7, 2, True, (32,), (1,)),
            NetArch("shallow128", 2, 32, 7, 2, True, (32, 64, 128), (1, 1, 1))]
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("fp8", 2e-3)])
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("fp8", 5e-3)])
 @pytest.mark.parametrize("arch", SHALLOW, ids=lambda a: a.name)
 def test_shallow_resnets_vs_emulation(arch, prec, tol):
     # every low-precision layer kind (stride-1 k7 with the tap-shift operand
