@@ -214,7 +214,13 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     static_assert(W_BYTES % 16 == 0 && (SLAB_EL * OPB) % 16 == 0, "16-byte LDS regions");
     constexpr int W_INST = (W_BYTES + 1023) / 1024;  // wave-wide 1 KB copies per chunk
     constexpr int NWAVES = WM * WN;
-    __shared__ __attribute__((aligned(16))) Op smem[NBUF * (SLAB_EL + W_EL)];
+    // the epilogue reuses the same LDS for the FP32 output tile [MT][NT + 4]
+    constexpr int EPITCH = NT + 4;
+    constexpr int BUF_BYTES = NBUF * (SLAB_EL + W_EL) * OPB;
+    constexpr int EPI_BYTES = MT * EPITCH * 4;
+    constexpr int SMEM_BYTES = BUF_BYTES > EPI_BYTES ? BUF_BYTES : EPI_BYTES;
+    __shared__ __attribute__((aligned(16))) unsigned char smem_raw[SMEM_BYTES];
+    Op* smem = (Op*)smem_raw;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -409,45 +415,91 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
 #undef AFM_WLOAD
 #undef AFM_STASH
 
-    // epilogue: dequant, bias, residual, ReLU, store, FP8 amax per window
+    // epilogue: the accumulators go through LDS so that bias, dequant,
+    // residual, ReLU, rounding and the stores run on 16-byte row vectors
+    __syncthreads();
+    float* et = (float*)smem_raw;
 #pragma unroll
-    for (int i = 0; i < TM; ++i) {
-        const int row0 = (wm * TM + i) * 16;        // 16 rows of one window
-        const int w = row0 / tt;
+    for (int i = 0; i < TM; ++i)
+#pragma unroll
+        for (int jn = 0; jn < TN; ++jn)
+#pragma unroll
+            for (int r = 0; r < 4; ++r)
+                et[((wm * TM + i) * 16 + g * 4 + r) * EPITCH + (wn * TN + jn) * 16 + r16] = acc[i][jn][r];
+    __syncthreads();
+    constexpr int VE = 16 / (int)sizeof(Act);   // outputs per 16-byte vector
+    constexpr int VPR = NT / VE;                // vectors per tile row
+    float vmax[WMAX];
+#pragma unroll
+    for (int u = 0; u < WMAX; ++u) vmax[u] = 0.f;
+    for (int v = tid; v < MT * VPR; v += NTH) {
+        const int row = v / VPR, col = (v % VPR) * VE;
+        const int w = row / tt;
         const int win = win0 + w;
-        const bool wvalid = win < a.n_win;
-        Act* out = (Act*)a.out + (size_t)win * a.L_out * a.C_out;
-        const Act* res = a.res ? (const Act*)a.res + (size_t)win * a.L_out * a.C_out : nullptr;
-        float vmax = 0.f;
+        const int t = t0 + row % tt;
+        if (win >= a.n_win || t >= a.L_out) continue;
+        const size_t o = ((size_t)win * a.L_out + t) * a.C_out + n0 + col;
+        float x[VE];
 #pragma unroll
-        for (int jn = 0; jn < TN; ++jn) {
-            const int col = n0 + (wn * TN + jn) * 16 + r16;
-            const float bcol = a.bias[col];
-            float deq = 1.f;
-            if constexpr (P::kFP8) {
-                float sw = s_a[0];
+        for (int e = 0; e < VE; ++e) x[e] = et[row * EPITCH + col + e];
+        float sa = 1.f;
+        if constexpr (P::kFP8) {
+            sa = s_a[0];
 #pragma unroll
-                for (int u = 1; u < WMAX; ++u) sw = (w == u) ? s_a[u] : sw;
-                deq = sw * a.wscale[col];
-            }
+            for (int u = 1; u < WMAX; ++u) sa = (w == u) ? s_a[u] : sa;
+        }
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                const int t = t0 + (row0 % tt) + g * 4 + r;
-                if (wvalid && t < a.L_out) {
-                    float v = P::kFP8 ? fmaf(acc[i][jn][r], deq, bcol) : acc[i][jn][r] + bcol;
-                    const size_t o = (size_t)t * a.C_out + col;
-                    if (res) v += act_to_f32<P>(res[o]);
-                    if (a.relu) v = fmaxf(v, 0.f);
-                    const Act sv = f32_to_act<P>(v);
-                    out[o] = sv;
-                    vmax = fmaxf(vmax, fabsf(act_to_f32<P>(sv)));
+        for (int e = 0; e < VE; ++e) {
+            const float b = a.bias[n0 + col + e];
+            x[e] = P::kFP8 ? fmaf(x[e], sa * a.wscale[n0 + col + e], b) : x[e] + b;
+        }
+        if (a.res) {
+            const uint4 rv = *(const uint4*)((const Act*)a.res + o);
+            if constexpr (sizeof(Act) == 4) {
+                x[0] += __uint_as_float(rv.x); x[1] += __uint_as_float(rv.y);
+                x[2] += __uint_as_float(rv.z); x[3] += __uint_as_float(rv.w);
+            } else {
+                const uint32_t wv[4] = {rv.x, rv.y, rv.z, rv.w};
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    x[2 * e] += __uint_as_float(wv[e] << 16);
+                    x[2 * e + 1] += __uint_as_float(wv[e] & 0xFFFF0000u);
                 }
             }
         }
+        if (a.relu) {
+#pragma unroll
+            for (int e = 0; e < VE; ++e) x[e] = fmaxf(x[e], 0.f);
+        }
+        uint4 ov;
+        float m = 0.f;
+        if constexpr (sizeof(Act) == 4) {
+            ov = make_uint4(__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3]));
+            m = fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3])));
+        } else {
+            uint32_t wv[4];
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const uint32_t lo = f32_to_bf16_bits(x[2 * e]), hi = f32_to_bf16_bits(x[2 * e + 1]);
+                wv[e] = lo | (hi << 16);
+                m = fmaxf(m, fmaxf(fabsf(__uint_as_float(lo << 16)), fabsf(__uint_as_float(hi << 16))));
+            }
+            ov = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        }
+        *(uint4*)((Act*)a.out + o) = ov;
         if constexpr (P::kFP8) {
-            if (a.amax_out) {
-                for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
-                if (lane == 0 && wvalid) atomicMax(&a.amax_out[win], __float_as_uint(vmax));
+#pragma unroll
+            for (int u = 0; u < WMAX; ++u)
+                if (w == u) vmax[u] = fmaxf(vmax[u], m);
+        }
+    }
+    if constexpr (P::kFP8) {
+        if (a.amax_out) {
+#pragma unroll
+            for (int u = 0; u < WMAX; ++u) {
+                float vm = vmax[u];
+                for (int off = 32; off > 0; off >>= 1) vm = fmaxf(vm, __shfl_xor(vm, off));
+                if (lane == 0 && u < wpt && win0 + u < a.n_win) atomicMax(&a.amax_out[win0 + u], __float_as_uint(vm));
             }
         }
     }
