@@ -154,12 +154,16 @@ struct ChunkGeom {
 };
 
 // Two packed BF16 words (4 values) -> 4 E4M3 bytes after scaling by sc.
+// gfx950's packed FP32 -> OCP E4M3 conversion rounds to nearest even like
+// f32_to_e4m3 (checked bit for bit on the device for |x| <= 448); the clamp
+// keeps it on the saturating side where it would otherwise return NaN.
 __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, float sc) {
-    const uint32_t b0 = f32_to_e4m3(__uint_as_float(lo2 << 16) * sc);
-    const uint32_t b1 = f32_to_e4m3(__uint_as_float(lo2 & 0xFFFF0000u) * sc);
-    const uint32_t b2 = f32_to_e4m3(__uint_as_float(hi2 << 16) * sc);
-    const uint32_t b3 = f32_to_e4m3(__uint_as_float(hi2 & 0xFFFF0000u) * sc);
-    return b0 | (b1 << 8) | (b2 << 16) | (b3 << 24);
+    auto q = [](float v) { return fminf(fmaxf(v, -448.f), 448.f); };
+    const float a = q(__uint_as_float(lo2 << 16) * sc), b = q(__uint_as_float(lo2 & 0xFFFF0000u) * sc);
+    const float c = q(__uint_as_float(hi2 << 16) * sc), d = q(__uint_as_float(hi2 & 0xFFFF0000u) * sc);
+    int r = __builtin_amdgcn_cvt_pk_fp8_f32(a, b, 0, false);
+    r = __builtin_amdgcn_cvt_pk_fp8_f32(c, d, r, true);
+    return (uint32_t)r;
 }
 
 // Implicit-GEMM conv on 16x16xMK MFMA tiles.
