@@ -46,7 +46,13 @@ typedef enum {
 typedef void* af_stream;   /* hipStream_t */
 
 typedef enum { AF_IN_F64 = 0, AF_IN_F32 = 1 } af_dtype;
-typedef enum { AF_F32 = 0, AF_BF16 = 1, AF_FP8 = 2 } af_precision;
+/* Conv arithmetic.  AF_F32: FP32 operands and activations.  AF_BF16: BF16
+ * operands and BF16 stored activations.  AF_FP8: E4M3 operands (per-channel
+ * weight scales, per-window activation scales), BF16 stored activations.
+ * AF_BF16_F32ACT: BF16 operands, FP32 stored activations (the residual
+ * stream keeps FP32; operands are rounded to BF16 as they are loaded).  All
+ * accumulate in FP32; the stem conv is FP32 in every mode. */
+typedef enum { AF_F32 = 0, AF_BF16 = 1, AF_FP8 = 2, AF_BF16_F32ACT = 3 } af_precision;
 
 /* Message describing the last error on this thread ("" if none). */
 const char* af_last_error(void);

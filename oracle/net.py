@@ -116,8 +116,12 @@ def _quant_conv(h, w, b, stride, precision):
 
 
 def net_forward_quant(params, arch, x, precision):
-    """Emulate the GPU's BF16 or FP8 network arithmetic; x [B, in_ch, window]
+    """Emulate the GPU's low-precision network arithmetic; x [B, in_ch, window]
     holds float32-representable values.  Returns logits [B] (float64).
+
+    'bf16f' (BF16 operands, FP32 activations): every stored tensor is rounded
+    to FP32 and each conv rounds its input to BF16 as the operand; otherwise
+    as 'bf16'.
 
     Stem: FP32 weights and input, vector arithmetic; its ReLU (and max-pool)
     output is stored as BF16.  Every other conv runs on the matrix cores with
@@ -128,25 +132,29 @@ def net_forward_quant(params, arch, x, precision):
     Projections are stored as BF16 before the add.  GAP and FC run in FP32 on
     the stored BF16 activations.
     """
-    if precision not in ("bf16", "fp8"):
+    if precision not in ("bf16", "fp8", "bf16f"):
         raise ValueError(precision)
     L = folded_layers(params, arch)
     relu = lambda v: np.maximum(v, 0.0)
+    store = _f32 if precision == "bf16f" else bf16_round
     w0, b0 = L["stem.conv"]
     h = relu(conv1d(x, _f32(w0), _f32(b0), stride=arch.stem_stride))
     if arch.stem_pool:
         h = maxpool3s2(h)
-    h = bf16_round(h)
+    h = store(h)
 
     def run(hin, name, stride):
         w, b = L[name]
-        acc, deq = _quant_conv(hin, w, b, stride, precision)
+        if precision == "bf16f":
+            acc, deq = _quant_conv(bf16_round(hin), w, b, stride, "bf16")
+        else:
+            acc, deq = _quant_conv(hin, w, b, stride, precision)
         bb = _f32(b)[None, :, None]
         return acc + bb if deq is None else acc * deq[:, :, None] + bb
 
     for pre, _, _, stride, proj in arch.block_list():
-        r = bf16_round(relu(run(h, pre + ".conv1", stride)))
-        skip = bf16_round(run(h, pre + ".proj", stride)) if proj else h
-        h = bf16_round(relu(run(r, pre + ".conv2", 1) + skip))
+        r = store(relu(run(h, pre + ".conv1", stride)))
+        skip = store(run(h, pre + ".proj", stride)) if proj else h
+        h = store(relu(run(r, pre + ".conv2", 1) + skip))
     g = h.mean(axis=2)
     return g @ _f32(params["fc.w"][0]) + _f32(params["fc.b"][0])[()]

@@ -18,7 +18,7 @@ __all__ = ["psd_estimate", "whiten", "Net", "integrate", "pack_params", "score_t
            "AframeError", "lib"]
 
 AF_IN_F64, AF_IN_F32 = 0, 1
-PRECISIONS = {"f32": 0, "bf16": 1, "fp8": 2}
+PRECISIONS = {"f32": 0, "bf16": 1, "fp8": 2, "bf16f": 3}
 
 
 def _stream(stream):

@@ -121,6 +121,10 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
         if (kc32) return cands_shape_lowp<PBF16, 32>(kw, s, c_out);
         return kw == 7 && s == 1 ? cands_lowp<PBF16, 7, 1, 16>(c_out) : Cands{};
     }
+    if (p == AF_BF16_F32ACT) {
+        if (kc32) return cands_shape_lowp<PBF16F, 32>(kw, s, c_out);
+        return kw == 7 && s == 1 ? cands_lowp<PBF16F, 7, 1, 16>(c_out) : Cands{};
+    }
     // FP8: k7 convs with >= 32-channel inputs on the 128-deep instruction
     // (a zero tap pads each 32-channel chunk from 224 to 256); 1x1 projections
     // and 16-channel inputs on the 32-deep one
@@ -191,7 +195,7 @@ void set_tiling(ConvOp& op) {
 // loads.  wscale: FP8 per-output-channel scales (FP64).
 std::vector<unsigned char> build_image(const ConvOp& op, const ConvCfg& cfg, af_precision prec,
                                        const std::vector<double>& wfold, const std::vector<double>& wscale) {
-    const size_t esz = prec == AF_F32 ? 4 : (prec == AF_BF16 ? 2 : 1);
+    const size_t esz = prec == AF_F32 ? 4 : (prec == AF_FP8 ? 1 : 2);
     const int NT = cfg.NT, KC = cfg.KC, KWP = cfg.KWP, PB = cfg.PB;
     const int KLs = cfg.KL, SWR = cfg.SWR, SWU = KC / cfg.KL;
     const int n_chunks = op.c_in / KC;
@@ -206,7 +210,7 @@ std::vector<unsigned char> build_image(const ConvOp& op, const ConvCfg& cfg, af_
                 const size_t e = (((size_t)nt * n_chunks + cc) * KWP * NT + row) * PB + cs;
                 const double v = wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
                 if (prec == AF_F32) ((float*)img.data())[e] = (float)v;
-                else if (prec == AF_BF16) ((uint16_t*)img.data())[e] = host_bf16_bits(v);
+                else if (prec == AF_BF16 || prec == AF_BF16_F32ACT) ((uint16_t*)img.data())[e] = host_bf16_bits(v);
                 else img[e] = host_e4m3_bits(v / wscale[op.b_off + o]);
             }
     }
@@ -250,7 +254,7 @@ struct af_net {
 };
 
 namespace {
-size_t act_size(af_precision p) { return p == AF_F32 ? 4 : 2; }
+size_t act_size(af_precision p) { return (p == AF_F32 || p == AF_BF16_F32ACT) ? 4 : 2; }
 
 void drop_records(af_net* n) {
     for (auto& r : n->recs) {
@@ -279,7 +283,8 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
                                    af_precision prec, af_net** out) {
     clear_error();
     AF_CHECK_ARG(d && params && out, "desc, params and out must be non-null");
-    AF_CHECK_ARG(prec == AF_F32 || prec == AF_BF16 || prec == AF_FP8, "unknown precision %d", (int)prec);
+    AF_CHECK_ARG(prec == AF_F32 || prec == AF_BF16 || prec == AF_FP8 || prec == AF_BF16_F32ACT,
+                 "unknown precision %d", (int)prec);
     AF_CHECK_ARG(d->in_ch >= 1 && d->in_ch <= 4, "in_ch must be in [1, 4]");
     AF_CHECK_ARG(d->kernel == 7, "only kernel 7 is implemented");
     AF_CHECK_ARG(d->stem_stride == 1 || d->stem_stride == 2, "stem_stride must be 1 or 2");
@@ -505,6 +510,7 @@ bool launch_stem_p(const af_net_desc& d, const StemArgs& sa, int nb, size_t lds,
 bool launch_stem(af_precision p, const af_net_desc& d, const StemArgs& sa, int nb, size_t lds, hipStream_t s) {
     if (p == AF_F32) return launch_stem_p<PF32>(d, sa, nb, lds, s);
     if (p == AF_BF16) return launch_stem_p<PBF16>(d, sa, nb, lds, s);
+    if (p == AF_BF16_F32ACT) return launch_stem_p<PF32>(d, sa, nb, lds, s);   // FP32 stem output
     return launch_stem_p<PFP8>(d, sa, nb, lds, s);
 }
 }  // namespace
@@ -627,7 +633,8 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         const size_t stem_lds = (size_t)n_ch * window * sizeof(float);
         if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
         if (!launch_stem(net->prec, d, sa, nb, stem_lds, s)) {
-            if (net->prec == AF_F32) hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
+            if (net->prec == AF_F32 || net->prec == AF_BF16_F32ACT)
+                hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
             else if (net->prec == AF_BF16) hipLaunchKernelGGL(stem_kernel<PBF16>, dim3(nb), dim3(256), stem_lds, s, sa);
             else hipLaunchKernelGGL(stem_kernel<PFP8>, dim3(nb), dim3(256), stem_lds, s, sa);
         }
@@ -657,7 +664,7 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             t_end();
         }
         if (!t_begin(layer + 1, nb)) { set_error("profiling event failed"); return AF_EHIP; }
-        if (net->prec == AF_F32)
+        if (act_size(net->prec) == 4)
             hipLaunchKernelGGL(gap_fc_kernel<PF32>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);
         else
             hipLaunchKernelGGL(gap_fc_kernel<PBF16>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);

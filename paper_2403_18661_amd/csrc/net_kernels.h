@@ -59,6 +59,14 @@ struct PFP8 {
     static constexpr int KL = 8;
     static constexpr bool kFP8 = true;
 };
+// BF16 operands with FP32 activations: every stored tensor (residual stream
+// included) stays FP32 and conv operands are rounded to BF16 as they are staged
+struct PBF16F {
+    using Act = float;
+    using Op = uint16_t;
+    static constexpr int KL = 8;
+    static constexpr bool kFP8 = false;
+};
 // FP8 on the 16x16x128 matrix instruction (32 k values per lane, unit block
 // scales): twice the FP8 rate of the 16x16x32 form
 struct PFP8X {
@@ -318,7 +326,14 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                 const int q = v % AV_ROW;                                                          \
                 const int rr = v / AV_ROW;                                                         \
                 Op* dst = slab_ + rr * PA + q * AE;                                                \
-                if constexpr (P::kFP8) {                                                           \
+                if constexpr (sizeof(Act) == 4 && sizeof(Op) == 2) {                               \
+                    const uint4 f = ra[i];                                                         \
+                    *(uint2*)dst = make_uint2(                                                     \
+                        (uint32_t)f32_to_bf16_bits(__uint_as_float(f.x)) |                         \
+                            ((uint32_t)f32_to_bf16_bits(__uint_as_float(f.y)) << 16),              \
+                        (uint32_t)f32_to_bf16_bits(__uint_as_float(f.z)) |                         \
+                            ((uint32_t)f32_to_bf16_bits(__uint_as_float(f.w)) << 16));             \
+                } else if constexpr (P::kFP8) {                                                    \
                     const int w = rr / srows;                                                      \
                     float sc = inv_a[0];                                                           \
                     _Pragma("unroll") for (int u = 1; u < WMAX; ++u) sc = (w == u) ? inv_a[u] : sc; \

@@ -12,9 +12,9 @@ from tests.gpu_util import banner, dev, need_gpu
 pytestmark = pytest.mark.gpu
 
 # logit tolerances against the FP64 oracle, per precision
-TOL = {"f32": 1e-3, "bf16": 3e-2, "fp8": 1e-1}
+TOL = {"f32": 1e-3, "bf16": 3e-2, "bf16f": 3e-2, "fp8": 1e-1}
 # tiny net against the quantisation-emulating oracle
-EMU_TOL = {"bf16": 2e-5, "fp8": 5e-4}
+EMU_TOL = {"bf16": 2e-5, "bf16f": 2e-5, "fp8": 5e-4}
 
 
 def series(n, seed, n_ch=2):
@@ -37,9 +37,11 @@ FP8_RESNET = pytest.param(
         "target; test_fp8_resnet_error_bound holds the measured level")))
 
 
-@pytest.mark.parametrize("arch,prec", [(TINY_ARCH, "f32"), (TINY_ARCH, "bf16"), (TINY_ARCH, "fp8"),
-                                       (RESNET_ARCH, "f32"), (RESNET_ARCH, "bf16"), FP8_RESNET],
-                         ids=["tiny-f32", "tiny-bf16", "tiny-fp8", "resnet-f32", "resnet-bf16", "resnet-fp8"])
+@pytest.mark.parametrize("arch,prec", [(TINY_ARCH, "f32"), (TINY_ARCH, "bf16"), (TINY_ARCH, "bf16f"),
+                                       (TINY_ARCH, "fp8"), (RESNET_ARCH, "f32"), (RESNET_ARCH, "bf16"),
+                                       (RESNET_ARCH, "bf16f"), FP8_RESNET],
+                         ids=["tiny-f32", "tiny-bf16", "tiny-bf16f", "tiny-fp8", "resnet-f32", "resnet-bf16",
+                              "resnet-bf16f", "resnet-fp8"])
 def test_logits_vs_fp64(arch, prec):
     P = need_gpu()
     banner(f"score {arch.name} {prec}")
@@ -170,7 +172,7 @@ SHALLOW = [NetArch("shallow32", 2, 32, 7, 2, True, (32,), (1,)),
            NetArch("shallow128", 2, 32, 7, 2, True, (32, 64, 128), (1, 1, 1))]
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("fp8", 5e-3)])
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("bf16f", 2e-4), ("fp8", 5e-3)])
 @pytest.mark.parametrize("arch", SHALLOW, ids=lambda a: a.name)
 def test_shallow_resnets_vs_emulation(arch, prec, tol):
     # every low-precision layer kind (stride-1 k7 with the tap-shift operand
