@@ -448,16 +448,32 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     __syncthreads();
     constexpr int VE = 16 / (int)sizeof(Act);   // outputs per 16-byte vector
     constexpr int VPR = NT / VE;                // vectors per tile row
+    constexpr int EPI_IT = (MT * VPR + NTH - 1) / NTH;
     float vmax[WMAX];
 #pragma unroll
     for (int u = 0; u < WMAX; ++u) vmax[u] = 0.f;
-    for (int v = tid; v < MT * VPR; v += NTH) {
+    // all residual loads first (a thread reads and later writes the same
+    // elements, so this also holds when the output overwrites the residual)
+    uint4 rres[EPI_IT];
+    size_t ooff[EPI_IT];
+    bool oval[EPI_IT];
+#pragma unroll
+    for (int it = 0; it < EPI_IT; ++it) {
+        const int v = tid + it * NTH;
         const int row = v / VPR, col = (v % VPR) * VE;
         const int w = row / tt;
-        const int win = win0 + w;
         const int t = t0 + row % tt;
-        if (win >= a.n_win || t >= a.L_out) continue;
-        const size_t o = ((size_t)win * a.L_out + t) * a.C_out + n0 + col;
+        oval[it] = v < MT * VPR && win0 + w < a.n_win && t < a.L_out;
+        ooff[it] = ((size_t)(win0 + w) * a.L_out + t) * a.C_out + n0 + col;
+        rres[it] = make_uint4(0u, 0u, 0u, 0u);
+        if (a.res && oval[it]) rres[it] = *(const uint4*)((const Act*)a.res + ooff[it]);
+    }
+#pragma unroll
+    for (int it = 0; it < EPI_IT; ++it) {
+        if (!oval[it]) continue;
+        const int v = tid + it * NTH;
+        const int row = v / VPR, col = (v % VPR) * VE;
+        const int w = row / tt;
         float x[VE];
 #pragma unroll
         for (int e = 0; e < VE; ++e) x[e] = et[row * EPITCH + col + e];
@@ -473,7 +489,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             x[e] = P::kFP8 ? fmaf(x[e], sa * a.wscale[n0 + col + e], b) : x[e] + b;
         }
         if (a.res) {
-            const uint4 rv = *(const uint4*)((const Act*)a.res + o);
+            const uint4 rv = rres[it];
             if constexpr (sizeof(Act) == 4) {
                 x[0] += __uint_as_float(rv.x); x[1] += __uint_as_float(rv.y);
                 x[2] += __uint_as_float(rv.z); x[3] += __uint_as_float(rv.w);
@@ -505,7 +521,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             }
             ov = make_uint4(wv[0], wv[1], wv[2], wv[3]);
         }
-        *(uint4*)((Act*)a.out + o) = ov;
+        *(uint4*)((Act*)a.out + ooff[it]) = ov;
         if constexpr (P::kFP8) {
 #pragma unroll
             for (int u = 0; u < WMAX; ++u)
