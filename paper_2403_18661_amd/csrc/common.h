@@ -47,6 +47,10 @@ inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 const double* twiddles_f64(int n);
 // Same table rounded to float.
 const float* twiddles_f32(int n);
+// Twiddles of one Stockham pass laid out in the order its butterflies use
+// them: image[(r - 1) ns + k] = exp(-2 pi i r k / n) for 1 <= r < rd, k < ns,
+// as interleaved float (re, im), built in FP64 on first use per device.
+const float* twiddle_image_f32(int n, int rd, int ns);
 
 // ---- device helpers ---------------------------------------------------------
 template <typename R>

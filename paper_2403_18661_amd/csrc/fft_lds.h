@@ -1,4 +1,5 @@
-// In-LDS complex FFT for one workgroup (Stockham autosort, radix 2/4/8/16).
+// In-LDS complex FFT for one workgroup (Stockham autosort, radix 2/4/8/16),
+// and the in-register DFTs (up to 32 points) that its passes are built from.
 //
 // The transform of length N = 2^LOGN lives in an LDS array of cpx<R>.  Every
 // pass reads the elements of its butterflies into registers, waits at a
@@ -19,18 +20,31 @@ namespace afm {
 __device__ __forceinline__ int lds_pad(int i) { return i + (i >> 4); }
 __host__ __device__ constexpr int lds_padded_len(int n) { return n + (n >> 4); }
 
-// exp(-2 pi i k / 16), k = 0..15 (cos, sin of multiples of pi/8)
-template <typename R>
-__device__ __forceinline__ cpx<R> w16(int k, bool inv) {
-    constexpr double C1 = 0.92387953251128675613;  // cos(pi/8)
-    constexpr double S1 = 0.38268343236508977173;  // sin(pi/8)
-    constexpr double H = 0.70710678118654752440;   // cos(pi/4)
-    const double c[16] = {1, C1, H, S1, 0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1};
-    const double s[16] = {0, -S1, -H, -C1, -1, -C1, -H, -S1, 0, S1, H, C1, 1, C1, H, S1};
-    return {(R)c[k & 15], (R)(inv ? -s[k & 15] : s[k & 15])};
+// cos(pi m / 16) for m = 0..8
+__device__ __forceinline__ constexpr double cos_pi16(int m) {
+    constexpr double C[9] = {1.0,
+                             0.98078528040323044913,  // cos(pi/16)
+                             0.92387953251128675613,  // cos(pi/8)
+                             0.83146961230254523708,  // cos(3 pi/16)
+                             0.70710678118654752440,  // cos(pi/4)
+                             0.55557023301960222474,  // cos(5 pi/16)
+                             0.38268343236508977173,  // cos(3 pi/8)
+                             0.19509032201612826785,  // cos(7 pi/16)
+                             0.0};
+    m &= 31;  // one period is 32 steps of pi/16
+    return m <= 8 ? C[m] : m <= 16 ? -C[16 - m] : m <= 24 ? -C[m - 16] : C[32 - m];
 }
 
-// In-register DFT of length RD (power of two <= 16) by radix-2 decimation in time.
+// exp(-2 pi i k / 32) (forward) or its conjugate (inverse), by symmetry from
+// the cosines above; k is a compile-time constant wherever this is used.
+template <typename R>
+__device__ __forceinline__ cpx<R> w32(int k, bool inv) {
+    const double c = cos_pi16(k);
+    const double s = cos_pi16(k + 24);  // sin(x) = cos(x - pi/2)
+    return {(R)c, (R)(inv ? s : -s)};
+}
+
+// In-register DFT of length RD (power of two <= 32) by radix-2 decimation in time.
 template <typename R, int RD>
 __device__ __forceinline__ void dft_reg(cpx<R>* v, bool inv) {
     if constexpr (RD == 1) {
@@ -50,7 +64,14 @@ __device__ __forceinline__ void dft_reg(cpx<R>* v, bool inv) {
         dft_reg<R, RD / 2>(o, inv);
 #pragma unroll
         for (int k = 0; k < RD / 2; ++k) {
-            cpx<R> t = (k == 0) ? o[k] : cmul(o[k], w16<R>(k * (16 / RD), inv));
+            const int m = k * (32 / RD);  // twiddle exp(-+2 pi i m / 32)
+            cpx<R> t;
+            if (m == 0)
+                t = o[k];
+            else if (m == 8)  // times -i (forward) or +i (inverse): no multiplies
+                t = inv ? cpx<R>{-o[k].y, o[k].x} : cpx<R>{o[k].y, -o[k].x};
+            else
+                t = cmul(o[k], w32<R>(m, inv));
             v[k] = cadd(e[k], t);
             v[k + RD / 2] = csub(e[k], t);
         }

@@ -18,4 +18,7 @@ int net_window(const af_net* net);
 int net_in_ch(const af_net* net);
 int net_device(const af_net* net);
 constexpr int kWhitenBlockOut = 6146;   // outputs per 8192-point block with a 2047-tap filter
+// floats of whitening response per PSD: one (sum, difference) pair per bin of
+// the 8192-point block grid for every detector pair
+inline int64_t whiten_resp_floats(int64_t n_ch) { return ((n_ch + 1) / 2) * 2 * (8192 / 2 + 1); }
 }  // namespace afm

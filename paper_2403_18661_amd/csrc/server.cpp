@@ -40,7 +40,7 @@ struct Stream {
     // device buffers
     double* raw = nullptr;     // [n_ch][cap_raw], absolute sample raw_base at column 0
     double* psd = nullptr;     // [2 slots][n_ch][F]
-    float* resp = nullptr;     // [2 slots][n_ch][RF]
+    float* resp = nullptr;     // [2 slots][whiten_resp_floats(n_ch)]
     float* logit = nullptr;    // [cap_logit], absolute logit logit_base at 0
     // progress (absolute indices)
     int64_t raw_base = 0, raw_count = 0;
@@ -140,7 +140,7 @@ af_status build_hop(af_server* s, Stream& st, int64_t h) {
     const af_server_config& c = s->cfg;
     const int64_t start = h * c.psd_hop - st.raw_base;
     double* psd = st.psd + (size_t)(h & 1) * s->n_ch * s->F;
-    float* resp = st.resp + (size_t)(h & 1) * s->n_ch * s->RF;
+    float* resp = st.resp + (size_t)(h & 1) * whiten_resp_floats(s->n_ch);
     af_status r = af_psd_estimate(st.raw + start, AF_IN_F64, s->n_ch, c.psd_len, s->cap_raw, c.fs, c.prescale,
                                   c.nperseg, c.noverlap, c.psd_len, 0, 1, psd, s->pgram_ws, s->pgram_bytes, s->stream);
     if (r != AF_OK) return r;
@@ -208,7 +208,7 @@ extern "C" af_status af_server_create(const af_net* net, const af_server_config*
     s->cap_logit = c.integrate_width + s->max_tick_windows + 16;
     s->ld_white = c.max_streams * s->cap_w;
     s->stream_bytes = (size_t)s->n_ch * s->cap_raw * 8 + (size_t)2 * s->n_ch * s->F * 8 +
-                      (size_t)2 * s->n_ch * s->RF * 4 + (size_t)s->cap_logit * 4;
+                      (size_t)2 * whiten_resp_floats(s->n_ch) * 4 + (size_t)s->cap_logit * 4;
     const int64_t max_windows = c.max_streams * s->max_tick_windows;
     s->pgram_bytes = af_psd_workspace_bytes(s->n_ch, c.nperseg, c.noverlap, c.psd_len, 0, 1);
     s->score_bytes = af_timeslide_workspace_bytes(net, 1, 1, std::min<int64_t>(c.score_batch, max_windows));
@@ -284,7 +284,7 @@ extern "C" af_status af_server_admit(af_server* s, int64_t* id) {
     st = Stream();
     if (hipMalloc((void**)&st.raw, (size_t)s->n_ch * s->cap_raw * 8) != hipSuccess ||
         hipMalloc((void**)&st.psd, (size_t)2 * s->n_ch * s->F * 8) != hipSuccess ||
-        hipMalloc((void**)&st.resp, (size_t)2 * s->n_ch * s->RF * 4) != hipSuccess ||
+        hipMalloc((void**)&st.resp, (size_t)2 * whiten_resp_floats(s->n_ch) * 4) != hipSuccess ||
         hipMalloc((void**)&st.logit, (size_t)s->cap_logit * 4) != hipSuccess) {
         free_stream(st);
         set_error("stream allocation failed");
@@ -404,7 +404,7 @@ extern "C" af_status af_server_tick(af_server* s, int64_t* n_windows) {
             }
             AF_CHECK_ARG(st.white_count + s->block - st.white_base <= s->cap_w, "stream %zu whitened buffer overflow", i);
             af_status r = whiten_apply(st.raw, AF_IN_F64, s->n_ch, st.raw_count - st.raw_base, s->cap_raw, c.prescale,
-                                       st.resp + (size_t)(h & 1) * s->n_ch * s->RF, 1, 0, s->M,
+                                       st.resp + (size_t)(h & 1) * whiten_resp_floats(s->n_ch), 1, 0, s->M,
                                        s->n0 + b * s->block - st.raw_base, s->block,
                                        s->white + i * s->cap_w + (st.white_count - st.white_base), s->ld_white,
                                        s->stream);

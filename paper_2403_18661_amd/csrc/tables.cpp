@@ -28,6 +28,7 @@ const char* last_error() { return g_err.c_str(); }
 namespace {
 std::mutex g_mu;
 std::map<std::pair<int, int>, void*> g_tw64, g_tw32;  // (device, n) -> table
+std::map<std::pair<int, long long>, void*> g_img;     // (device, packed n/rd/ns) -> table
 
 std::vector<double> host_twiddles(int n) {
     // exp(-2 pi i t / n) evaluated in FP64 from the definition
@@ -71,6 +72,31 @@ const float* twiddles_f32(int n) {
     if (hipMalloc(&d, f.size() * sizeof(float)) != hipSuccess) return nullptr;
     if (hipMemcpy(d, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
     g_tw32[key] = d;
+    return (const float*)d;
+}
+
+const float* twiddle_image_f32(int n, int rd, int ns) {
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return nullptr;
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto key = std::make_pair(dev, ((long long)n << 32) | ((long long)rd << 16) | (long long)ns);
+    auto it = g_img.find(key);
+    if (it != g_img.end()) return (const float*)it->second;
+    // image[(r - 1) ns + k] = exp(-2 pi i r k / n), from the definition in FP64
+    const double two_pi = 6.283185307179586476925286766559;
+    std::vector<float> f(2 * (size_t)(rd - 1) * ns);
+    for (int r = 1; r < rd; ++r)
+        for (int k = 0; k < ns; ++k) {
+            const long long m = ((long long)r * k) % n;
+            const double a = -two_pi * (double)m / (double)n;
+            const size_t i = 2 * ((size_t)(r - 1) * ns + k);
+            f[i] = (float)std::cos(a);
+            f[i + 1] = (float)std::sin(a);
+        }
+    void* d = nullptr;
+    if (hipMalloc(&d, f.size() * sizeof(float)) != hipSuccess) return nullptr;
+    if (hipMemcpy(d, f.data(), f.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess) return nullptr;
+    g_img[key] = d;
     return (const float*)d;
 }
 
