@@ -147,6 +147,9 @@ def main():
     ap.add_argument("--no-timeslide", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--layers-out", default=None, help="write per-layer timings and tiles to this JSON file")
+    ap.add_argument("--calib-copy-mb", type=int, default=0,
+                    help="before anything else, run one plain device copy of this many MiB (a known-size "
+                         "reference for hardware byte counters)")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
@@ -166,6 +169,14 @@ def main():
     from synth.workloads import hour_strain, PSD_LEN
 
     arch = RESNET_ARCH
+    if args.calib_copy_mb > 0:
+        src = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy of {args.calib_copy_mb} MiB done")
+        del src, dst
     log("generating 1 h workload")
     x, inj = hour_strain(seed=0, n_windows=args.windows)
     params = make_params(arch, seed=0)
@@ -242,6 +253,13 @@ def main():
                             "stages_ms": r["stages_ms"]}
     h = res[head]
     n_launch = h["conv"]["launches_per_step"]
+    # HBM bytes per conv launch from the committed FETCH_SIZE / WRITE_SIZE
+    # passes; empty once the kernel sources differ from the profiled ones
+    from paper_2403_18661_amd.profsum import read_traffic
+    pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                    "conv_mfma_hour_workload.txt"))
+    for prec in precisions:
+        precisions[prec]["conv_traffic_bytes_per_launch"] = pmc.get(prec, {}).get("traffic")
     # the metric's comparison: fastest reduced-precision mode whose integrated
     # statistic keeps Kendall tau >= 0.99 against the FP32 run
     ok = [(p, r) for p, r in precisions.items() if p != head and r["tau_vs_f32"] is not None
@@ -261,7 +279,7 @@ def main():
                    "windows_per_step": int(args.windows), "batch": args.batch, "injections": len(inj)},
         "roofline": {"bound": "mfma", "kernel": "conv_mfma_kernel (all 35 MFMA conv launches of a batch)",
                      "achieved": h["conv"]["tflops"], "peak": PEAK_TFLOPS[head], "unit": "TFLOP/s",
-                     "frac": h["conv"]["frac"], "traffic": None,
+                     "frac": h["conv"]["frac"], "traffic": pmc.get(head, {}).get("traffic"),
                      "avg_launch_ms": h["conv"]["ms_per_step"] / max(n_launch, 1),
                      "launches_per_step": n_launch},
         "whiten_roofline": {"bound": "hbm", "achieved": h["whiten_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
