@@ -23,12 +23,25 @@ __global__ void __launch_bounds__(NT) welch_periodogram_kernel(
     const int64_t c0 = 2 * (int64_t)blockIdx.y;
     const bool has1 = c0 + 1 < n_ch;
     const TX* x0 = x + c0 * ld_x + g * step;
-    const TX* x1 = x + (c0 + 1) * ld_x + g * step;
-    for (int t = threadIdx.x; t < N; t += NT) {
-        const double w = 0.5 - 0.5 * tw[t].x;  // periodic Hann, cos(2 pi t / N)
-        const double v0 = (double)x0[t] * prescale * w;
-        const double v1 = has1 ? (double)x1[t] * prescale * w : 0.0;
-        a[lds_pad(t)] = {v0, v1};
+    const TX* x1 = has1 ? x0 + ld_x : x0;
+    {
+        // all loads issued before the first use
+        constexpr int PER = N / NT;
+        TX u0[PER], u1[PER];
+        double c[PER];
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int t = threadIdx.x + p * NT;
+            u0[p] = x0[t];
+            u1[p] = x1[t];
+            c[p] = tw[t].x;  // cos(2 pi t / N)
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const double w = 0.5 - 0.5 * c[p];  // periodic Hann
+            a[lds_pad(threadIdx.x + p * NT)] = {(double)u0[p] * prescale * w,
+                                                has1 ? (double)u1[p] * prescale * w : 0.0};
+        }
     }
     __syncthreads();
     fft_lds<double, LOGN, NT>(a, tw, false);
@@ -55,8 +68,17 @@ __global__ void welch_average_kernel(const double* __restrict__ pgram, int64_t n
     const int64_t j = idx / ((int64_t)F * n_ch);
     const double* p = pgram + ((j * hop_seg) * n_ch + c) * F + k;
     const int64_t stride = n_ch * (int64_t)F;
+    // summed in segment order; loads issued 16 at a time ahead of the sums
     double s = 0.0;
-    for (int64_t i = 0; i < n_avg; ++i) s += p[i * stride];
+    int64_t i = 0;
+    for (; i + 16 <= n_avg; i += 16) {
+        double v[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) v[u] = p[(i + u) * stride];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) s += v[u];
+    }
+    for (; i < n_avg; ++i) s += p[i * stride];
     const double ck = (k == 0 || k == F - 1) ? 1.0 : 2.0;
     psd[idx] = s / (double)n_avg * scale * ck;
 }

@@ -74,18 +74,26 @@ __global__ void __launch_bounds__(NT) fir_response_kernel(
     constexpr int PER = WB_N / NT;
     cpx<double> g[PER];
     const double invL = 1.0 / (double)L;
+    const int tstep = WB_N / (2 * M);  // M is a power of two <= L / 2
+    {
+        // taper cosines first (all loads in flight), then the taps
+        double cs[PER];
 #pragma unroll
-    for (int p = 0; p < PER; ++p) {
-        const int t = threadIdx.x + p * NT;
-        int m = t < M ? t : (t > WB_N - M ? t - WB_N : WB_N);
-        if (m == WB_N) {
-            g[p] = {0.0, 0.0};
-        } else {
+        for (int p = 0; p < PER; ++p) {
+            const int t = threadIdx.x + p * NT;
+            const int m = t < M ? t : t - WB_N;  // tap index of position t when |m| < M
             const int am = m < 0 ? -m : m;
             // (1 + cos(pi m / M)) / 2 with cos(pi m / M) = Re exp(-2 pi i (m WB_N / 2M) / WB_N)
-            const double taper = 0.5 * (1.0 + twB[am * (WB_N / (2 * M))].x);
-            cpx<double> q = a[lds_pad(((m % L) + L) % L)];
-            g[p] = {q.x * invL * taper, q.y * invL * taper};
+            cs[p] = twB[am < M ? am * tstep : 0].x;
+        }
+#pragma unroll
+        for (int p = 0; p < PER; ++p) {
+            const int t = threadIdx.x + p * NT;
+            const int m = t < M ? t : t - WB_N;
+            const bool tap = m > -M && m < M;
+            const cpx<double> q = a[lds_pad(m & (L - 1))];  // q[m mod L]
+            const double w = tap ? 0.5 * (1.0 + cs[p]) * invL : 0.0;
+            g[p] = {q.x * w, q.y * w};
         }
     }
     __syncthreads();
