@@ -9,6 +9,7 @@
 namespace afm {
 
 typedef float f4v __attribute__((ext_vector_type(4)));
+typedef uint32_t u4v __attribute__((ext_vector_type(4)));  // 16-byte staging vector
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---- scalar conversions -----------------------------------------------------
@@ -215,8 +216,13 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     constexpr int SLAB_EL = SLAB_ROWS * PA;
     constexpr int W_EL = KWP * NT * PB;
     constexpr int NBUF = DB ? 2 : 1;
-    // slab: 16-byte vectors through registers; weights: the chunk's LDS image
-    // (padding included) copied with direct global->LDS 16-byte loads
+    // slab: 16-byte vectors through registers.  Weights (the chunk's LDS image,
+    // padding included): with DB also through registers, loaded at the start
+    // of the chunk before and written to LDS at its end, since a direct
+    // global->LDS copy in flight makes every LDS read of the current chunk
+    // wait for it (the wait counters cannot tell the two buffers apart);
+    // without DB nothing overlaps, and direct global->LDS copies save the
+    // registers
     constexpr int AE = 16 / (int)sizeof(Act);   // activations per 16-byte load
     constexpr int AV_ROW = KC / AE;             // vectors per slab row
     static_assert(KC % AE == 0, "slab rows must be whole 16-byte vectors");
@@ -224,7 +230,9 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     constexpr int RA = (AV_MAX + NTH - 1) / NTH;  // slab vectors per thread (upper bound)
     constexpr int W_BYTES = W_EL * OPB;           // one chunk's weight image
     static_assert(W_BYTES % 16 == 0 && (SLAB_EL * OPB) % 16 == 0, "16-byte LDS regions");
-    constexpr int W_INST = (W_BYTES + 1023) / 1024;  // wave-wide 1 KB copies per chunk
+    constexpr int WV = W_BYTES / 16;              // 16-byte vectors of the weight image
+    constexpr int RW = DB ? (WV + NTH - 1) / NTH : 1;  // weight vectors per thread (DB)
+    constexpr int W_INST = (W_BYTES + 1023) / 1024;    // wave-wide 1 KB copies (no DB)
     constexpr int NWAVES = WM * WN;
     // the epilogue reuses the same LDS for the FP32 output tile [MT][NT + 4]
     constexpr int EPITCH = NT + 4;
@@ -306,8 +314,14 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             ra[i] = x;                                                                             \
         }                                                                                          \
     }
-#define AFM_WLOAD(CC, BUF)                                                                         \
-    {                                                                                              \
+#define AFM_WLOAD(RWV, CC, BUF)                                                                    \
+    if constexpr (DB) {                                                                            \
+        const uint4* src_ = (const uint4*)(wimg + (size_t)(CC) * W_BYTES);                        \
+        _Pragma("unroll") for (int i = 0; i < RW; ++i) {                                          \
+            const int u = tid + i * NTH;                                                           \
+            if (WV % NTH == 0 || u < WV) RWV[i] = *(const u4v*)(src_ + u);                        \
+        }                                                                                          \
+    } else {                                                                                       \
         const char* src_ = wimg + (size_t)(CC) * W_BYTES;                                          \
         char* dst_ = (char*)(smem + (BUF) * (SLAB_EL + W_EL) + SLAB_EL);                           \
         for (int i = wave; i < W_INST; i += NWAVES) {                                              \
@@ -317,9 +331,16 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                                                  (__attribute__((address_space(3))) void*)(dst_ + i * 1024), 16, 0, 0); \
         }                                                                                          \
     }
-#define AFM_STASH(BUF)                                                                             \
+#define AFM_STASH(RWV, BUF)                                                                        \
     {                                                                                              \
         Op* slab_ = smem + (BUF) * (SLAB_EL + W_EL);                                               \
+        if constexpr (DB) {                                                                        \
+            uint4* wdst_ = (uint4*)(slab_ + SLAB_EL);                                              \
+            _Pragma("unroll") for (int i = 0; i < RW; ++i) {                                      \
+                const int u = tid + i * NTH;                                                       \
+                if (WV % NTH == 0 || u < WV) *(u4v*)(wdst_ + u) = RWV[i];                          \
+            }                                                                                      \
+        }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
             const int v = tid + i * NTH;                                                           \
             if (v < av_count) {                                                                    \
@@ -346,16 +367,20 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
         }                                                                                          \
     }
 
-    AFM_FETCH(0)
-    AFM_WLOAD(0, 0)
-    AFM_STASH(0)
+    {
+        u4v rw[RW];
+        AFM_FETCH(0)
+        AFM_WLOAD(rw, 0, 0)
+        AFM_STASH(rw, 0)
+    }
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int cc = 0; cc < n_chunks; ++cc) {
         const int buf = DB ? (cc & 1) : 0;
+        u4v rw[RW];  // the next chunk's weights (DB), loaded now, stored to LDS after the MFMAs
         if (DB && cc + 1 < n_chunks) {
             AFM_FETCH(cc + 1)
-            AFM_WLOAD(cc + 1, buf ^ 1)
+            AFM_WLOAD(rw, cc + 1, buf ^ 1)
         }
         const Op* slab = smem + buf * (SLAB_EL + W_EL);
         const Op* wl = slab + SLAB_EL;
@@ -418,14 +443,14 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                 for (int jn = 0; jn < TN; ++jn) mfma_step<P>(acc[i][jn], ab[i], bb[jn]);
         }
         if (DB) {
-            if (cc + 1 < n_chunks) AFM_STASH(buf ^ 1)
+            if (cc + 1 < n_chunks) AFM_STASH(rw, buf ^ 1)
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         } else if (cc + 1 < n_chunks) {
             __syncthreads();
             AFM_FETCH(cc + 1)
-            AFM_WLOAD(cc + 1, 0)
-            AFM_STASH(0)
+            AFM_WLOAD(rw, cc + 1, 0)
+            AFM_STASH(rw, 0)
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
         }
