@@ -25,18 +25,19 @@ struct ConvCfg {
     int SWR = 0;  // rows per swizzle step (0: no swizzle)
 };
 
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS>
 void launch_conv(const ConvArgs& a, hipStream_t s) {
     constexpr int MT = WM * TM * 16, NT = WN * TN * 16;
     const unsigned gx = a.wpt == 1 ? (unsigned)(a.n_win * a.tiles_per_win) : (unsigned)((a.n_win + a.wpt - 1) / a.wpt);
-    hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB>), dim3(gx, (unsigned)(a.C_out / NT)),
-                       dim3(64 * WM * WN), 0, s, a);
+    hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB, TS>),
+                       dim3(gx, (unsigned)(a.C_out / NT)), dim3(64 * WM * WN), 0, s, a);
 }
 
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
+// TS: allow the tap-shift A-operand reuse where the kernel supports it.
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS = true>
 ConvCfg make_cfg() {
     ConvCfg c;
-    c.fn = launch_conv<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB>;
+    c.fn = launch_conv<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB, TS>;
     c.MT = WM * TM * 16;
     c.NT = WN * TN * 16;
     c.KC = KC;
@@ -86,10 +87,12 @@ Cands cands_lowp(int c_out) {
         constexpr bool DB_WIDE = !(KW == 7 && S == 2);
         if (c_out % 128 == 0)
             return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
-                    make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>()};
+                    make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>()};
         if (c_out == 64)
             return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
-                    make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>()};
+                    make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>()};
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>()};

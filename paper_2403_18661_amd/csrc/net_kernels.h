@@ -4,6 +4,7 @@
 // implicit-GEMM row for output time t reads the contiguous input rows
 // t*S - (KW-1)/2 ... t*S + (KW-1)/2 of the window.
 #pragma once
+#include <type_traits>
 #include "common.h"
 
 namespace afm {
@@ -127,6 +128,33 @@ __device__ __forceinline__ void mfma_regs(f4v& acc, const uint32_t (&a)[D], cons
     }
 }
 
+// One lane's MFMA operand for the 16-bit and 8-bit forms, read from LDS into
+// registers ahead of the product that uses it.
+template <typename P>
+struct Frag {
+    typedef int i32x8 __attribute__((ext_vector_type(8)));
+    using T = std::conditional_t<P::kFP8, std::conditional_t<P::KL == 32, i32x8, long>, bf16x8>;
+};
+template <typename P>
+__device__ __forceinline__ typename Frag<P>::T load_frag(const typename P::Op* p) {
+    using T = typename Frag<P>::T;
+    if constexpr (sizeof(T) == 32) {
+        const uint4 x0 = ((const uint4*)p)[0], x1 = ((const uint4*)p)[1];
+        return T{(int)x0.x, (int)x0.y, (int)x0.z, (int)x0.w, (int)x1.x, (int)x1.y, (int)x1.z, (int)x1.w};
+    } else {
+        return *(const T*)p;
+    }
+}
+template <typename P>
+__device__ __forceinline__ void mfma_frag(f4v& acc, const typename Frag<P>::T& a, const typename Frag<P>::T& b) {
+    if constexpr (P::kFP8 && P::KL == 32)
+        acc = __builtin_amdgcn_mfma_scale_f32_16x16x128_f8f6f4(a, b, acc, 0, 0, 0, 127, 0, 127);
+    else if constexpr (P::kFP8)
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_fp8_fp8(a, b, acc, 0, 0, 0);
+    else
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc, 0, 0, 0);
+}
+
 template <int D, typename T>
 __device__ __forceinline__ void load_words(uint32_t (&w)[D], const T* p) {
     if constexpr (D == 4) {
@@ -183,7 +211,7 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, floa
 // and the chunk's weights are staged in LDS with 16-byte loads; tap j then
 // reads the slab shifted by j rows.  With DB the next chunk is fetched into
 // registers while the current one is multiplied (two LDS buffers).
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB>
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS = true>
 __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     using Op = typename P::Op;
     using Act = typename P::Act;
@@ -206,7 +234,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     constexpr int SWU = KC / KL;                                    // units per row
     constexpr int SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
     // tap-shift reuse of the A operand (see the k-loop)
-    constexpr bool SHIFT = S == 1 && KW > 1 && MK == KC && KPAD == KW * KC && OPB <= 2 && KL == 8;
+    constexpr bool SHIFT = TS && S == 1 && KW > 1 && MK == KC && KPAD == KW * KC && OPB <= 2 && KL == 8;
     constexpr int PAD = (KW - 1) / 2;
     // rows of all windows' slabs: wpt windows need (MT - wpt) S + wpt KWP rows,
     // largest at wpt = WMAX when KWP >= S and at wpt = 1 otherwise (1x1, stride 2)
@@ -422,6 +450,33 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                     }
                 }
             }
+        } else if constexpr (OPB <= 2) {
+            // two-stage register pipeline: the fragments of k-step s + 1 are
+            // read from LDS before the MFMAs of step s are issued
+            using FT = typename Frag<P>::T;
+            constexpr int NS = KPAD / MK;
+            FT fa[2][TM], fb[2][TN];
+            auto load_step = [&](int ks, FT (&xa)[TM], FT (&xb)[TN]) {
+                const int k = ks * MK + g * KL;
+                const int j = k / KC, c = k % KC;
+#pragma unroll
+                for (int i = 0; i < TM; ++i) xa[i] = load_frag<P>(slab + arow[i] + j * PA + c);
+#pragma unroll
+                for (int jn = 0; jn < TN; ++jn) {
+                    const int row = j * NT + (wn * TN + jn) * 16 + r16;
+                    const int cs = SWR ? (((c / KL) ^ ((row / (SWR ? SWR : 1)) & (SWU - 1))) * KL) : c;
+                    xb[jn] = load_frag<P>(wl + row * PB + cs);
+                }
+            };
+            load_step(0, fa[0], fb[0]);
+#pragma unroll
+            for (int st = 0; st < NS; ++st) {
+                if (st + 1 < NS) load_step(st + 1, fa[(st + 1) & 1], fb[(st + 1) & 1]);
+#pragma unroll
+                for (int i = 0; i < TM; ++i)
+#pragma unroll
+                    for (int jn = 0; jn < TN; ++jn) mfma_frag<P>(acc[i][jn], fa[st & 1][i], fb[st & 1][jn]);
+            }
         } else
 #pragma unroll
         for (int ks = 0; ks < KPAD; ks += MK) {
@@ -482,6 +537,16 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
     uint4 rres[EPI_IT];
     size_t ooff[EPI_IT];
     bool oval[EPI_IT];
+    // NTH is a multiple of VPR, so a thread's columns are the same in every
+    // iteration: its bias (and FP8 weight scales) are loaded once
+    static_assert(NTH % VPR == 0, "epilogue columns must not depend on the iteration");
+    const int col_t = (tid % VPR) * VE;
+    float bcol[VE], scol[VE];
+#pragma unroll
+    for (int e = 0; e < VE; ++e) {
+        bcol[e] = a.bias[n0 + col_t + e];
+        scol[e] = P::kFP8 ? a.wscale[n0 + col_t + e] : 1.f;
+    }
 #pragma unroll
     for (int it = 0; it < EPI_IT; ++it) {
         const int v = tid + it * NTH;
@@ -493,15 +558,30 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
         rres[it] = make_uint4(0u, 0u, 0u, 0u);
         if (a.res && oval[it]) rres[it] = *(const uint4*)((const Act*)a.res + ooff[it]);
     }
+    // BF16/FP8 operands: every tile row read from LDS first (rows < MT: always
+    // in range), so the reads of all iterations are in flight together and
+    // only stores are guarded.  FP32 reads per iteration instead: the extra
+    // registers would cost its kernels a wave per SIMD.
+    constexpr bool XPRE = OPB <= 2;
+    float xt[XPRE ? EPI_IT : 1][VE];
+    if constexpr (XPRE) {
+#pragma unroll
+        for (int it = 0; it < EPI_IT; ++it) {
+            const int v = tid + it * NTH;
+            const int row = (v < MT * VPR ? v : 0) / VPR;
+#pragma unroll
+            for (int e = 0; e < VE; ++e) xt[it][e] = et[row * EPITCH + col_t + e];
+        }
+    }
 #pragma unroll
     for (int it = 0; it < EPI_IT; ++it) {
         if (!oval[it]) continue;
         const int v = tid + it * NTH;
-        const int row = v / VPR, col = (v % VPR) * VE;
+        const int row = v / VPR;
         const int w = row / tt;
         float x[VE];
 #pragma unroll
-        for (int e = 0; e < VE; ++e) x[e] = et[row * EPITCH + col + e];
+        for (int e = 0; e < VE; ++e) x[e] = XPRE ? xt[XPRE ? it : 0][e] : et[row * EPITCH + col_t + e];
         float sa = 1.f;
         if constexpr (P::kFP8) {
             sa = s_a[0];
@@ -509,10 +589,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             for (int u = 1; u < WMAX; ++u) sa = (w == u) ? s_a[u] : sa;
         }
 #pragma unroll
-        for (int e = 0; e < VE; ++e) {
-            const float b = a.bias[n0 + col + e];
-            x[e] = P::kFP8 ? fmaf(x[e], sa * a.wscale[n0 + col + e], b) : x[e] + b;
-        }
+        for (int e = 0; e < VE; ++e) x[e] = P::kFP8 ? fmaf(x[e], sa * scol[e], bcol[e]) : x[e] + bcol[e];
         if (a.res) {
             const uint4 rv = rres[it];
             if constexpr (sizeof(Act) == 4) {
