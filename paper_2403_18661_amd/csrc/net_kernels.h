@@ -325,20 +325,36 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
         arow[i] = (w * srows + t * S) * PA;
     }
 
+    // slab vectors of this thread: source offset from the tile's first window
+    // (without the chunk's channel offset), LDS offset, validity and (FP8)
+    // scale, all chunk-independent
+    const Act* in_t = in + (size_t)win0 * a.L_in * a.C_in;
+    int f_off[RA];
+    int s_off[RA];
+    bool f_ok[RA], s_ok[RA];
+    float s_sc[RA];
+#pragma unroll
+    for (int i = 0; i < RA; ++i) {
+        const int v = tid + i * NTH;
+        const int q = v % AV_ROW;
+        const int rr = v / AV_ROW;
+        const int w = rr / srows, r = rr % srows;
+        const int gr = t0 * S - PAD + r;
+        const int win = win0 + w;
+        s_ok[i] = v < av_count;
+        f_ok[i] = s_ok[i] && win < a.n_win && gr >= 0 && gr < a.L_in;
+        f_off[i] = f_ok[i] ? (w * a.L_in + gr) * a.C_in + q * AE : 0;
+        s_off[i] = rr * PA + q * AE;
+        float sc = inv_a[0];
+#pragma unroll
+        for (int u = 1; u < WMAX; ++u) sc = (w == u) ? inv_a[u] : sc;
+        s_sc[i] = sc;
+    }
 #define AFM_FETCH(CC)                                                                              \
     {                                                                                              \
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
-            const int v = tid + i * NTH;                                                           \
             uint4 x = make_uint4(0u, 0u, 0u, 0u);                                                  \
-            if (v < av_count) {                                                                    \
-                const int q = v % AV_ROW;                                                          \
-                const int rr = v / AV_ROW;                                                         \
-                const int w = rr / srows, r = rr % srows;                                          \
-                const int gr = t0 * S - PAD + r;                                                   \
-                const int win = win0 + w;                                                          \
-                if (win < a.n_win && gr >= 0 && gr < a.L_in)                                       \
-                    x = *(const uint4*)(in + ((size_t)win * a.L_in + gr) * a.C_in + (CC) * KC + q * AE); \
-            }                                                                                      \
+            if (f_ok[i]) x = *(const uint4*)(in_t + f_off[i] + (CC) * KC);                         \
             ra[i] = x;                                                                             \
         }                                                                                          \
     }
@@ -370,11 +386,8 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
             }                                                                                      \
         }                                                                                          \
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
-            const int v = tid + i * NTH;                                                           \
-            if (v < av_count) {                                                                    \
-                const int q = v % AV_ROW;                                                          \
-                const int rr = v / AV_ROW;                                                         \
-                Op* dst = slab_ + rr * PA + q * AE;                                                \
+            if (s_ok[i]) {                                                                         \
+                Op* dst = slab_ + s_off[i];                                                        \
                 if constexpr (sizeof(Act) == 4 && sizeof(Op) == 2) {                               \
                     const uint4 f = ra[i];                                                         \
                     *(uint2*)dst = make_uint2(                                                     \
@@ -383,9 +396,7 @@ __global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
                         (uint32_t)f32_to_bf16_bits(__uint_as_float(f.z)) |                         \
                             ((uint32_t)f32_to_bf16_bits(__uint_as_float(f.w)) << 16));             \
                 } else if constexpr (P::kFP8) {                                                    \
-                    const int w = rr / srows;                                                      \
-                    float sc = inv_a[0];                                                           \
-                    _Pragma("unroll") for (int u = 1; u < WMAX; ++u) sc = (w == u) ? inv_a[u] : sc; \
+                    const float sc = s_sc[i];                                                      \
                     *(uint2*)dst = make_uint2(pack_e4m3x4(ra[i].x, ra[i].y, sc),                    \
                                               pack_e4m3x4(ra[i].z, ra[i].w, sc));                   \
                 } else {                                                                           \
