@@ -88,14 +88,18 @@ Cands cands_lowp(int c_out) {
         if (c_out % 128 == 0)
             return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>()};
+                    make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, false, false>()};
         if (c_out == 64)
             return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>()};
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, false, false>()};
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
-                return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>()};
+                return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>(),
+                        make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, false, false>(),
+                        make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, false, false>()};
         }
         return {};
     }
@@ -129,9 +133,21 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
         return kw == 7 && s == 1 ? cands_lowp<PBF16F, 7, 1, 16>(c_out) : Cands{};
     }
     // FP8: k7 convs with >= 32-channel inputs on the 128-deep instruction
-    // (a zero tap pads each 32-channel chunk from 224 to 256); 1x1 projections
-    // and 16-channel inputs on the 32-deep one
-    if (kc32 && kw == 7) return cands_shape_lowp<PFP8X, 32>(kw, s, c_out);
+    // (a zero tap pads each 32-channel chunk from 224 to 256), plus
+    // single-buffered tiles on the 32-deep one (no padding tap, 8-byte
+    // operands: two workgroups fit a CU); 1x1 projections and 16-channel
+    // inputs on the 32-deep one
+    if (kc32 && kw == 7) {
+        Cands c = cands_shape_lowp<PFP8X, 32>(kw, s, c_out);
+        if (s == 1 && c_out == 32) {
+            c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 2, 2, 32, 1, false, false>());
+            c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 4, 2, 32, 1, false, false>());
+        } else if (c_out % 64 == 0) {
+            if (s == 1) c.push_back(make_cfg<PFP8, 7, 1, 2, 2, 6, 2, 32, 2, false, false>());
+            if (s == 2) c.push_back(make_cfg<PFP8, 7, 2, 2, 2, 6, 2, 32, 2, false, false>());
+        }
+        return c;
+    }
     if (kc32) return kw == 1 && s == 2 && c_out >= 64 ? cands_lowp<PFP8, 1, 2, 32>(c_out) : Cands{};
     return kw == 7 && s == 1 ? cands_lowp<PFP8, 7, 1, 16>(c_out) : Cands{};
 }
