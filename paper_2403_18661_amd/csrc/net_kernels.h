@@ -211,8 +211,17 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, floa
 // and the chunk's weights are staged in LDS with 16-byte loads; tap j then
 // reads the slab shifted by j rows.  With DB the next chunk is fetched into
 // registers while the current one is multiplied (two LDS buffers).
+// Waves per SIMD the register allocation aims for: three for the small
+// single-buffered 16/8-bit tiles with 16- or 8-byte operands (whose LDS lets
+// three workgroups share a CU), otherwise the compiler's choice.
+template <typename P, int WM, int WN, int TM, int TN, bool DB>
+constexpr int conv_waves_per_eu() {
+    return (!DB && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64) ? 3 : 1;
+}
+
 template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS = true>
-__global__ void __launch_bounds__(64 * WM * WN) conv_mfma_kernel(ConvArgs a) {
+__global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM, TN, DB>()))
+    conv_mfma_kernel(ConvArgs a) {
     using Op = typename P::Op;
     using Act = typename P::Act;
     constexpr int KL = P::KL;
