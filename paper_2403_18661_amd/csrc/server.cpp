@@ -125,6 +125,10 @@ void free_server(af_server* s) {
 
 // Move columns [from, to) of a [n_ch][ld] buffer (element size esz) to column 0.
 af_status compact(af_server* s, void* buf, int64_t ld, int64_t from, int64_t to, size_t esz) {
+    if (from < 0 || to < from) {
+        set_error("internal error: compaction range [%lld, %lld)", (long long)from, (long long)to);
+        return AF_EINVAL;
+    }
     const int64_t len = to - from;
     if (from == 0 || len <= 0) return AF_OK;
     for (int c = 0; c < s->n_ch; ++c) {
@@ -139,6 +143,10 @@ af_status compact(af_server* s, void* buf, int64_t ld, int64_t from, int64_t to,
 af_status build_hop(af_server* s, Stream& st, int64_t h) {
     const af_server_config& c = s->cfg;
     const int64_t start = h * c.psd_hop - st.raw_base;
+    if (start < 0 || start + c.psd_len > st.raw_count - st.raw_base) {
+        set_error("internal error: PSD background of hop %lld is not in the raw buffer", (long long)h);
+        return AF_EINVAL;
+    }
     double* psd = st.psd + (size_t)(h & 1) * s->n_ch * s->F;
     float* resp = st.resp + (size_t)(h & 1) * whiten_resp_floats(s->n_ch);
     af_status r = af_psd_estimate(st.raw + start, AF_IN_F64, s->n_ch, c.psd_len, s->cap_raw, c.fs, c.prescale,
@@ -363,11 +371,13 @@ extern "C" af_status af_server_tick(af_server* s, int64_t* n_windows) {
         for (const Chunk& ch : taken[i]) incoming += ch.n;
         if (incoming > 0) {
             if (st.raw_count + incoming - st.raw_base > s->cap_raw) {
-                // keep what the next hop's PSD and the next whitening block need
+                // keep what the next whitening block needs (from n0 + b*block - M)
+                // and what the next PSD to build needs (hop psd_done reads its
+                // background from psd_done*psd_hop, which lies psd_len - psd_hop
+                // before its first block's context)
                 const int64_t b = st.white_count / s->block;
-                const int64_t h = (b * s->block) / c.psd_hop;
                 int64_t keep = s->n0 + b * s->block - s->M;
-                if (h >= st.psd_done) keep = std::min<int64_t>(keep, h * c.psd_hop);
+                keep = std::min<int64_t>(keep, st.psd_done * c.psd_hop);
                 keep = std::min(keep, st.raw_count);
                 af_status r = compact(s, st.raw, s->cap_raw, keep - st.raw_base, st.raw_count - st.raw_base, 8);
                 if (r != AF_OK) return r;
@@ -403,6 +413,8 @@ extern "C" af_status af_server_tick(af_server* s, int64_t* n_windows) {
                 st.white_base = keep;
             }
             AF_CHECK_ARG(st.white_count + s->block - st.white_base <= s->cap_w, "stream %zu whitened buffer overflow", i);
+            AF_CHECK_ARG(s->n0 + b * s->block - s->M >= st.raw_base,
+                         "internal error: whitening context of stream %zu is not in the raw buffer", i);
             af_status r = whiten_apply(st.raw, AF_IN_F64, s->n_ch, st.raw_count - st.raw_base, s->cap_raw, c.prescale,
                                        st.resp + (size_t)(h & 1) * whiten_resp_floats(s->n_ch), 1, 0, s->M,
                                        s->n0 + b * s->block - st.raw_base, s->block,

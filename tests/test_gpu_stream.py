@@ -63,6 +63,28 @@ def test_stream_equals_offline():
     np.testing.assert_allclose(out[1], ig[:m], atol=1e-4)
 
 
+def test_stream_long_equals_offline():
+    """150 s in 1 s chunks: the raw ring (about 85 s) is compacted several
+    times, and every later PSD and whitening block must still see its data."""
+    P = need_gpu()
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from paper_2403_18661_amd.stream import Server
+    banner("stream vs offline, 150 s (raw ring compaction)")
+    params = make_params(TINY_ARCH, seed=35)
+    net = P.Net(TINY_ARCH, params, "f32")
+    x = coloured_noise(FS * 150, seed=36)
+    srv = Server(net, max_streams=2, hbm_budget=4 << 30)
+    sid = srv.admit()
+    out = run_stream(srv, {sid: x}, lambda r: FS, np.random.default_rng(3))[sid]
+    path = OfflinePath(net, x.shape[1], PathConfig(psd_len=64 * FS))
+    path.run(torch.from_numpy(x).cuda())
+    lg, ig = path.logits.cpu().numpy(), path.integrated.cpu().numpy()
+    n, m = len(out[0]), len(out[1])
+    assert n > 16 * 80 and n <= len(lg)
+    np.testing.assert_allclose(out[0], lg[:n], atol=1e-4)
+    np.testing.assert_allclose(out[1], ig[:m], atol=1e-4)
+
+
 def test_alone_equals_in_the_mix():
     P = need_gpu()
     from paper_2403_18661_amd.stream import Server
