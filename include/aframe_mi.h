@@ -106,6 +106,25 @@ af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t
                     int64_t out_start, int64_t n_out, float* y, int64_t ld_y,
                     void* ws, size_t ws_bytes, af_stream stream);
 
+/* The two halves of af_whiten, for callers that reuse filters (one rolling
+ * PSD serving several output spans) or time them apart.
+ * af_whiten_response builds the filters of n_psd PSDs (FP64 on the device,
+ * stored as float) into resp: device memory of at least
+ * af_whiten_workspace_bytes(n_ch, nperseg, n_psd) bytes, caller-owned, whose
+ * layout is private to the library.
+ * af_whiten_apply convolves x with filters made by af_whiten_response for the
+ * same n_ch, fs and fduration; x, n, ld_x, prescale, n_psd, psd_hop,
+ * out_start, n_out, y and ld_y mean what they mean for af_whiten and are
+ * checked the same way.  Both return AF_EINVAL before any launch on a bad
+ * argument or a buffer that is too small. */
+af_status af_whiten_response(const double* psd, int64_t n_ch, int64_t nperseg, int64_t n_psd, double fs,
+                             double fduration, double highpass, void* resp, size_t resp_bytes,
+                             af_stream stream);
+af_status af_whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double fs,
+                          double prescale, const void* resp, size_t resp_bytes, int64_t n_psd,
+                          int64_t psd_hop, double fduration, int64_t out_start, int64_t n_out, float* y,
+                          int64_t ld_y, af_stream stream);
+
 /* ------------------------------------------------------------------------
  * Scoring network (Sec. II: 1D-convolutional ResNet mapping a two-detector
  * window to one scalar detection statistic).  Architecture: stem conv (kernel

@@ -88,6 +88,37 @@ def whiten(x, psd, fs, prescale=1.0, psd_hop=0, fduration=1.0, highpass=32.0, ou
     return out
 
 
+def whiten_response(psd, fs, fduration=1.0, highpass=32.0, out=None, stream=None):
+    """Whitening filters of psd [n_psd, n_ch, F] into a device buffer
+    (af_whiten_response); pass it to whiten_apply."""
+    _check_dev(psd, "psd", (torch.float64,))
+    if psd.dim() == 2:
+        psd = psd.unsqueeze(0)
+    n_psd, n_ch, F = psd.shape
+    nperseg = 2 * (F - 1)
+    need = lib().af_whiten_workspace_bytes(n_ch, nperseg, n_psd)
+    out = _workspace(need, psd.device) if out is None else out
+    check(lib().af_whiten_response(_ptr(psd.contiguous()), n_ch, nperseg, n_psd, fs, fduration, highpass, _ptr(out),
+                                   out.numel(), _stream(stream)))
+    return out
+
+
+def whiten_apply(x, resp, n_psd, fs, prescale=1.0, psd_hop=0, fduration=1.0, out_start=None, n_out=None, out=None,
+                 stream=None):
+    """Whiten x [n_ch, n] with filters from whiten_response (af_whiten_apply)."""
+    _check_dev(x, "x", (torch.float64, torch.float32))
+    n_ch, n = x.shape
+    M = int(round(fduration * fs / 2))
+    out_start = M if out_start is None else out_start
+    n_out = n - out_start - M if n_out is None else n_out
+    if out is None:
+        out = torch.empty((n_ch, n_out), dtype=torch.float32, device=x.device)
+    check(lib().af_whiten_apply(_ptr(x), _in_dtype(x), n_ch, n, x.stride(0), fs, prescale, _ptr(resp), resp.numel(),
+                                n_psd, psd_hop, fduration, out_start, n_out, _ptr(out), out.stride(0),
+                                _stream(stream)))
+    return out
+
+
 def pack_params(params, arch):
     """Flatten a name -> array parameter dict into the C ABI's order: per conv
     (stem; per block conv1, conv2, [proj]) weight then BN gamma, beta, mean,

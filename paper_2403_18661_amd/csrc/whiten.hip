@@ -361,7 +361,7 @@ namespace {
 constexpr int FIR_NT = 512;
 constexpr size_t FIR_LDS = (size_t)lds_padded_len(WB_N) * sizeof(cpx<double>);
 
-size_t resp_bytes(int64_t n_ch, int64_t n_psd) {
+size_t resp_bytes_for(int64_t n_ch, int64_t n_psd) {
     return align_up((size_t)n_psd * whiten_resp_floats(n_ch) * sizeof(float), 256);
 }
 
@@ -380,7 +380,7 @@ hipError_t launch_fir(const double* psd, int64_t n_ch, int64_t n_psd, double fs,
 
 extern "C" size_t af_whiten_workspace_bytes(int64_t n_ch, int64_t nperseg, int64_t n_psd) {
     if (n_ch < 1 || n_psd < 1 || (nperseg != 2048 && nperseg != 4096)) return 0;
-    return resp_bytes(n_ch, n_psd);
+    return resp_bytes_for(n_ch, n_psd);
 }
 
 namespace afm {
@@ -429,35 +429,91 @@ af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int6
 }
 }  // namespace afm
 
+namespace {
+// M = fduration*fs/2 taps per side: a power of two with 2M <= nperseg whose
+// filter leaves valid outputs in an 8192-point block.
+af_status whiten_taps(double fs, double fduration, int64_t nperseg, int* M_out) {
+    const double Md = fduration * fs / 2.0;
+    const int M = (int)llround(Md);
+    AF_CHECK_ARG(fabs(Md - M) < 1e-9 && M >= 2 && (M & (M - 1)) == 0 && 2 * M <= nperseg,
+                 "fduration*fs/2 must be a power of two M with 2M <= nperseg (got %g)", Md);
+    AF_CHECK_ARG(WB_N - 2 * (M - 1) > 0, "filter too long for the %d-point whitening block", WB_N);
+    *M_out = M;
+    return AF_OK;
+}
+
+af_status whiten_check_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
+                             int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out, const float* y,
+                             int64_t ld_y) {
+    AF_CHECK_ARG(x && y, "x and y must be non-null");
+    AF_CHECK_ARG(xt == AF_IN_F64 || xt == AF_IN_F32, "unknown input dtype %d", (int)xt);
+    AF_CHECK_ARG(n_ch >= 1 && n >= 1 && ld_x >= n, "need n_ch >= 1, n >= 1, ld_x >= n");
+    AF_CHECK_ARG(prescale > 0, "prescale must be > 0");
+    AF_CHECK_ARG(n_psd >= 1, "n_psd must be >= 1");
+    AF_CHECK_ARG(n_out >= 1 && ld_y >= n_out, "need n_out >= 1 and ld_y >= n_out");
+    AF_CHECK_ARG(out_start >= M && out_start + n_out + M <= n,
+                 "output range [%lld, %lld) needs %d samples of context on each side within n = %lld",
+                 (long long)out_start, (long long)(out_start + n_out), M, (long long)n);
+    if (n_psd > 1)
+        AF_CHECK_ARG(psd_hop >= 1 && (n_psd - 1) * psd_hop < n_out,
+                     "psd_hop must be >= 1 and every PSD hop must start inside the output");
+    return AF_OK;
+}
+}  // namespace
+
+extern "C" af_status af_whiten_response(const double* psd, int64_t n_ch, int64_t nperseg, int64_t n_psd, double fs,
+                                        double fduration, double highpass, void* resp, size_t resp_bytes,
+                                        af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(psd && resp, "psd and resp must be non-null");
+    AF_CHECK_ARG(n_ch >= 1 && n_psd >= 1, "need n_ch >= 1 and n_psd >= 1");
+    AF_CHECK_ARG(fs > 0 && highpass >= 0, "fs must be > 0 and highpass >= 0");
+    AF_CHECK_ARG(nperseg == 2048 || nperseg == 4096, "nperseg must be 2048 or 4096 (got %lld)", (long long)nperseg);
+    int M = 0;
+    af_status st = whiten_taps(fs, fduration, nperseg, &M);
+    if (st != AF_OK) return st;
+    const size_t need = resp_bytes_for(n_ch, n_psd);
+    AF_CHECK_ARG(resp_bytes >= need, "response buffer too small: need %zu bytes, got %zu", need, resp_bytes);
+    return whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, (float*)resp, (hipStream_t)stream);
+}
+
+extern "C" af_status af_whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double fs,
+                                     double prescale, const void* resp, size_t resp_bytes, int64_t n_psd,
+                                     int64_t psd_hop, double fduration, int64_t out_start, int64_t n_out, float* y,
+                                     int64_t ld_y, af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(resp, "resp must be non-null");
+    AF_CHECK_ARG(fs > 0, "fs must be > 0");
+    int M = 0;
+    af_status st = whiten_taps(fs, fduration, 4096, &M);
+    if (st != AF_OK) return st;
+    st = whiten_check_apply(x, xt, n_ch, n, ld_x, prescale, n_psd, psd_hop, M, out_start, n_out, y, ld_y);
+    if (st != AF_OK) return st;
+    const size_t need = resp_bytes_for(n_ch, n_psd);
+    AF_CHECK_ARG(resp_bytes >= need, "response buffer too small: need %zu bytes, got %zu", need, resp_bytes);
+    return whiten_apply(x, xt, n_ch, n, ld_x, prescale, (const float*)resp, n_psd, psd_hop, M, out_start, n_out, y,
+                        ld_y, (hipStream_t)stream);
+}
+
 extern "C" af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x,
                                double fs, double prescale, const double* psd, int64_t nperseg,
                                int64_t n_psd, int64_t psd_hop, double fduration, double highpass,
                                int64_t out_start, int64_t n_out, float* y, int64_t ld_y, void* ws,
                                size_t ws_bytes, af_stream stream) {
     clear_error();
-    AF_CHECK_ARG(x && psd && y, "x, psd and y must be non-null");
-    AF_CHECK_ARG(xt == AF_IN_F64 || xt == AF_IN_F32, "unknown input dtype %d", (int)xt);
-    AF_CHECK_ARG(n_ch >= 1 && n >= 1 && ld_x >= n, "need n_ch >= 1, n >= 1, ld_x >= n");
-    AF_CHECK_ARG(fs > 0 && prescale > 0 && highpass >= 0, "fs, prescale must be > 0 and highpass >= 0");
+    AF_CHECK_ARG(psd, "psd must be non-null");
+    AF_CHECK_ARG(fs > 0 && highpass >= 0, "fs must be > 0 and highpass >= 0");
     AF_CHECK_ARG(nperseg == 2048 || nperseg == 4096, "nperseg must be 2048 or 4096 (got %lld)", (long long)nperseg);
-    const double Md = fduration * fs / 2.0;
-    const int M = (int)llround(Md);
-    AF_CHECK_ARG(fabs(Md - M) < 1e-9 && M >= 2 && (M & (M - 1)) == 0 && 2 * M <= nperseg,
-                 "fduration*fs/2 must be a power of two M with 2M <= nperseg (got %g)", Md);
-    AF_CHECK_ARG(n_psd >= 1, "n_psd must be >= 1");
-    AF_CHECK_ARG(n_out >= 1 && ld_y >= n_out, "need n_out >= 1 and ld_y >= n_out");
-    AF_CHECK_ARG(out_start >= M && out_start + n_out + M <= n,
-                 "output range [%lld, %lld) needs %d samples of context on each side within n = %lld",
-                 (long long)out_start, (long long)(out_start + n_out), M, (long long)n);
-    AF_CHECK_ARG(WB_N - 2 * (M - 1) > 0, "filter too long for the %d-point whitening block", WB_N);
-    if (n_psd > 1)
-        AF_CHECK_ARG(psd_hop >= 1 && (n_psd - 1) * psd_hop < n_out,
-                     "psd_hop must be >= 1 and every PSD hop must start inside the output");
-    const size_t need = resp_bytes(n_ch, n_psd);
+    int M = 0;
+    af_status st = whiten_taps(fs, fduration, nperseg, &M);
+    if (st != AF_OK) return st;
+    st = whiten_check_apply(x, xt, n_ch, n, ld_x, prescale, n_psd, psd_hop, M, out_start, n_out, y, ld_y);
+    if (st != AF_OK) return st;
+    const size_t need = resp_bytes_for(n_ch, n_psd);
     AF_CHECK_ARG(ws && ws_bytes >= need, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
     hipStream_t s = (hipStream_t)stream;
     float* resp = (float*)ws;
-    af_status st = whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, resp, s);
+    st = whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, resp, s);
     if (st != AF_OK) return st;
     return whiten_apply(x, xt, n_ch, n, ld_x, prescale, resp, n_psd, psd_hop, M, out_start, n_out, y, ld_y, s);
 }

@@ -12,7 +12,7 @@ from dataclasses import dataclass
 
 import torch
 
-from . import Net, integrate, lib, psd_estimate, whiten, _workspace
+from . import Net, integrate, lib, psd_estimate, whiten_apply, whiten_response, _workspace
 
 
 @dataclass(frozen=True)
@@ -63,10 +63,20 @@ class OfflinePath:
         return psd_estimate(x, c.fs, c.prescale, c.nperseg, c.noverlap, self.psd_len, self.psd_hop, self.n_psd,
                             out=self.psd, ws=self.ws_psd, stream=stream)
 
-    def whiten_stage(self, x, stream=None):
+    def response_stage(self, stream=None):
+        """Whitening filters of every PSD hop (af_whiten_response)."""
         c = self.cfg
-        return whiten(x, self.psd, c.fs, c.prescale, self.psd_hop if self.n_psd > 1 else 0, c.fduration,
-                      c.highpass, self.out_start, self.n_out, out=self.y, ws=self.ws_wh, stream=stream)
+        return whiten_response(self.psd, c.fs, c.fduration, c.highpass, out=self.ws_wh, stream=stream)
+
+    def apply_stage(self, x, stream=None):
+        """Overlap-save whitening with the hops' filters (af_whiten_apply)."""
+        c = self.cfg
+        return whiten_apply(x, self.ws_wh, self.n_psd, c.fs, c.prescale, self.psd_hop if self.n_psd > 1 else 0,
+                            c.fduration, self.out_start, self.n_out, out=self.y, stream=stream)
+
+    def whiten_stage(self, x, stream=None):
+        self.response_stage(stream)
+        return self.apply_stage(x, stream)
 
     def score_stage(self, stream=None):
         return self.net.score_windows(self.y, self.cfg.stride, self.n_windows, out=self.logits, ws=self.ws_net,

@@ -24,7 +24,8 @@ import hashlib
 import os
 import re
 
-KERNEL_SOURCES = ("csrc/net_kernels.h", "csrc/net.hip", "csrc/fused_tiny.h")
+KERNEL_SOURCES = ("csrc/net_kernels.h", "csrc/net.hip", "csrc/fused_tiny.h", "csrc/whiten.hip", "csrc/psd.hip",
+                  "csrc/fft_lds.h")
 
 
 def source_sha256():

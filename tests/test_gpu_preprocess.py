@@ -136,3 +136,30 @@ def test_integrate(n, width):
     ref = oracle.integrate(p.astype(np.float64), width)
     assert got.shape == ref.shape
     np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-6)
+
+
+def test_whiten_response_apply_split():
+    """af_whiten_response + af_whiten_apply = af_whiten bit for bit (rolling
+    PSDs, FP64 input); undersized buffers are rejected before any launch."""
+    P = need_gpu()
+    banner("whiten split response/apply")
+    import torch
+    fs = int(FS)
+    x = coloured_noise(fs * 96, seed=77)
+    xd = dev(x)
+    hop = 8 * fs
+    n_psd = 3
+    psd = P.psd_estimate(xd, FS, PRESCALE, psd_len=64 * fs, psd_hop=hop, n_psd=n_psd)
+    M = fs // 2
+    out_start = 64 * fs + M
+    n_out = xd.shape[1] - out_start - M
+    ref = P.whiten(xd, psd, FS, PRESCALE, hop, out_start=out_start, n_out=n_out)
+    resp = P.whiten_response(psd, FS)
+    got = P.whiten_apply(xd, resp, n_psd, FS, PRESCALE, hop, out_start=out_start, n_out=n_out)
+    torch.cuda.synchronize()
+    assert torch.equal(got, ref)
+    small = resp[: resp.numel() // 2]
+    with pytest.raises(P.AframeError):
+        P.whiten_apply(xd, small, n_psd, FS, PRESCALE, hop, out_start=out_start, n_out=n_out)
+    with pytest.raises(P.AframeError):
+        P.whiten_response(psd, FS, out=small)
