@@ -113,7 +113,9 @@ Cands cands_shape_lowp(int kw, int s, int c_out) {
     return {};
 }
 
-Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
+// role: 1 for the first conv of a residual block (it writes the block's inner
+// activation), 2 for the second (it reads it), 0 for any other conv
+Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int role) {
     if (p == AF_F32) {
         if (c_in % 16 != 0) return {};
         if (kw == 7 && s == 1) return cands_f32<7, 1>(c_out);
@@ -129,6 +131,17 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
         return kw == 7 && s == 1 ? cands_lowp<PBF16, 7, 1, 16>(c_out) : Cands{};
     }
     if (p == AF_BF16_F32ACT) {
+        // A block's inner activation feeds only the block's second conv, which
+        // rounds it to a BF16 operand as it loads it; the first conv stores it
+        // as BF16 directly (the same rounding of the same FP32 value), halving
+        // its traffic without changing a bit of the result.  The first conv is
+        // k7 with stride 1 or 2, the second k7 with stride 1.
+        if (role == 1 && kw == 7) {
+            if (s == 1) return kc32 ? cands_lowp<PBF16FB, 7, 1, 32>(c_out) : cands_lowp<PBF16FB, 7, 1, 16>(c_out);
+            return kc32 && c_out >= 64 ? cands_lowp<PBF16FB, 7, 2, 32>(c_out) : Cands{};
+        }
+        if (role == 2 && kw == 7 && s == 1)
+            return kc32 ? cands_lowp<PBF16BF, 7, 1, 32>(c_out) : cands_lowp<PBF16BF, 7, 1, 16>(c_out);
         if (kc32) return cands_shape_lowp<PBF16F, 32>(kw, s, c_out);
         return kw == 7 && s == 1 ? cands_lowp<PBF16F, 7, 1, 16>(c_out) : Cands{};
     }
@@ -273,6 +286,7 @@ struct af_net {
 };
 
 namespace {
+// bytes per stored activation (every buffer is sized for the widest kind)
 size_t act_size(af_precision p) { return (p == AF_F32 || p == AF_BF16_F32ACT) ? 4 : 2; }
 
 void drop_records(af_net* n) {
@@ -365,7 +379,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         op.amax_out = n_slots++;
         op.w_off = wfold.size();
         op.b_off = bias.size();
-        op.cands = conv_candidates(prec, kw, s, c_in, c_out);
+        op.cands = conv_candidates(prec, kw, s, c_in, c_out, out_buf == BR ? 1 : (in_buf == BR ? 2 : 0));
         op.cand = 0;
         op.cfg = op.cands.empty() ? ConvCfg{} : op.cands[0];
         if (!op.cfg.fn) {

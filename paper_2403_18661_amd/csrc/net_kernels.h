@@ -41,22 +41,26 @@ __device__ __forceinline__ uint8_t f32_to_e4m3(float v) {
 }
 
 // ---- precision traits -----------------------------------------------------------
-// Act: stored activation element; Op: LDS operand element; KL: k values per
-// lane per MFMA; MK = 4 KL: k per MFMA (16x16xMK).
+// Act: stored activation element a conv reads; OAct: the one it writes (and
+// its residual input); Op: LDS operand element; KL: k values per lane per
+// MFMA; MK = 4 KL: k per MFMA (16x16xMK).
 struct PF32 {
     using Act = float;
+    using OAct = float;
     using Op = float;
     static constexpr int KL = 1;
     static constexpr bool kFP8 = false;
 };
 struct PBF16 {
     using Act = uint16_t;
+    using OAct = uint16_t;
     using Op = uint16_t;
     static constexpr int KL = 8;
     static constexpr bool kFP8 = false;
 };
 struct PFP8 {
     using Act = uint16_t;  // activations are stored as BF16 and quantised on load
+    using OAct = uint16_t;
     using Op = uint8_t;
     static constexpr int KL = 8;
     static constexpr bool kFP8 = true;
@@ -65,6 +69,26 @@ struct PFP8 {
 // included) stays FP32 and conv operands are rounded to BF16 as they are staged
 struct PBF16F {
     using Act = float;
+    using OAct = float;
+    using Op = uint16_t;
+    static constexpr int KL = 8;
+    static constexpr bool kFP8 = false;
+};
+// The same arithmetic with a block's inner activation stored as BF16: the
+// first conv of a block reads the FP32 stream and writes its output already
+// rounded the way the second conv would round it on load (PBF16FB); the
+// second reads that BF16 tensor and writes the FP32 stream, adding the FP32
+// skip (PBF16BF)
+struct PBF16FB {
+    using Act = float;
+    using OAct = uint16_t;
+    using Op = uint16_t;
+    static constexpr int KL = 8;
+    static constexpr bool kFP8 = false;
+};
+struct PBF16BF {
+    using Act = uint16_t;
+    using OAct = float;
     using Op = uint16_t;
     static constexpr int KL = 8;
     static constexpr bool kFP8 = false;
@@ -73,6 +97,7 @@ struct PBF16F {
 // scales): twice the FP8 rate of the 16x16x32 form
 struct PFP8X {
     using Act = uint16_t;
+    using OAct = uint16_t;
     using Op = uint8_t;
     static constexpr int KL = 32;
     static constexpr bool kFP8 = true;
@@ -224,6 +249,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     conv_mfma_kernel(ConvArgs a) {
     using Op = typename P::Op;
     using Act = typename P::Act;
+    using OAct = typename P::OAct;
     constexpr int KL = P::KL;
     constexpr int MK = 4 * KL;
     constexpr int MT = WM * TM * 16;
@@ -546,7 +572,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
             for (int r = 0; r < 4; ++r)
                 et[((wm * TM + i) * 16 + g * 4 + r) * EPITCH + (wn * TN + jn) * 16 + r16] = acc[i][jn][r];
     __syncthreads();
-    constexpr int VE = 16 / (int)sizeof(Act);   // outputs per 16-byte vector
+    constexpr int VE = 16 / (int)sizeof(OAct);   // outputs per 16-byte vector
     constexpr int VPR = NT / VE;                // vectors per tile row
     constexpr int EPI_IT = (MT * VPR + NTH - 1) / NTH;
     float vmax[WMAX];
@@ -576,7 +602,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         oval[it] = v < MT * VPR && win0 + w < a.n_win && t < a.L_out;
         ooff[it] = ((size_t)(win0 + w) * a.L_out + t) * a.C_out + n0 + col;
         rres[it] = make_uint4(0u, 0u, 0u, 0u);
-        if (a.res && oval[it]) rres[it] = *(const uint4*)((const Act*)a.res + ooff[it]);
+        if (a.res && oval[it]) rres[it] = *(const uint4*)((const OAct*)a.res + ooff[it]);
     }
     // BF16/FP8 operands: every tile row read from LDS first (rows < MT: always
     // in range), so the reads of all iterations are in flight together and
@@ -612,7 +638,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         for (int e = 0; e < VE; ++e) x[e] = P::kFP8 ? fmaf(x[e], sa * scol[e], bcol[e]) : x[e] + bcol[e];
         if (a.res) {
             const uint4 rv = rres[it];
-            if constexpr (sizeof(Act) == 4) {
+            if constexpr (sizeof(OAct) == 4) {
                 x[0] += __uint_as_float(rv.x); x[1] += __uint_as_float(rv.y);
                 x[2] += __uint_as_float(rv.z); x[3] += __uint_as_float(rv.w);
             } else {
@@ -630,7 +656,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         }
         uint4 ov;
         float m = 0.f;
-        if constexpr (sizeof(Act) == 4) {
+        if constexpr (sizeof(OAct) == 4) {
             ov = make_uint4(__float_as_uint(x[0]), __float_as_uint(x[1]), __float_as_uint(x[2]), __float_as_uint(x[3]));
             m = fmaxf(fmaxf(fabsf(x[0]), fabsf(x[1])), fmaxf(fabsf(x[2]), fabsf(x[3])));
         } else {
@@ -643,7 +669,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
             }
             ov = make_uint4(wv[0], wv[1], wv[2], wv[3]);
         }
-        *(uint4*)((Act*)a.out + ooff[it]) = ov;
+        *(uint4*)((OAct*)a.out + ooff[it]) = ov;
         if constexpr (P::kFP8) {
 #pragma unroll
             for (int u = 0; u < WMAX; ++u)

@@ -150,7 +150,7 @@ def test_fused_unavailable_for_fp32():
         net.fused = True
 
 
-@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16f"])
 def test_autotune_keeps_logits(prec):
     # switching tile shapes leaves every window's arithmetic unchanged
     P = need_gpu()
