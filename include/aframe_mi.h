@@ -197,6 +197,11 @@ af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_t ws_bytes,
  * rows (mt) and output channels (nt) per workgroup, candidate count, chosen index. */
 af_status af_net_layer_tile(const af_net* net, int64_t layer, int32_t* mt, int32_t* nt, int32_t* n_candidates,
                             int32_t* chosen);
+/* Use tile candidate `chosen` (0 <= chosen < n_candidates) for conv layer
+ * `layer`, e.g. to replay an earlier autotuning without timing again.  Waits
+ * for the device, then rebuilds the layer's weight image; logits are the same
+ * bit for bit under every candidate.  AF_EINVAL for a bad layer or index. */
+af_status af_net_set_layer_tile(af_net* net, int64_t layer, int32_t chosen);
 
 /* Workspace needed to score `batch` windows per internal pass. */
 size_t af_score_workspace_bytes(const af_net* net, int64_t batch);

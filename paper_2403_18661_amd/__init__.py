@@ -224,6 +224,11 @@ class Net:
             out.append(tuple(x.value for x in v))
         return out
 
+    def set_tile(self, layer, chosen):
+        """Use tile candidate `chosen` for conv layer `layer` (1 = first conv;
+        af_net_set_layer_tile)."""
+        check(lib().af_net_set_layer_tile(self._h, layer, chosen))
+
     def workspace_bytes(self, batch):
         return lib().af_score_workspace_bytes(self._h, batch)
 

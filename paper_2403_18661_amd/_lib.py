@@ -46,6 +46,7 @@ SIGNATURES = {
     "af_net_n_layers": (c_i64, [c_vp]),
     "af_net_fused": (c_int, [c_vp]),
     "af_net_autotune": (c_int, [c_vp, c_i64, c_vp, c_sz, c_vp, ctypes.POINTER(c_i64)]),
+    "af_net_set_layer_tile": (c_int, [c_vp, c_i64, ctypes.c_int32]),
     "af_net_layer_tile": (c_int, [c_vp, c_i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "af_net_set_fused": (c_int, [c_vp, c_int]),

@@ -25,16 +25,19 @@ struct ConvCfg {
     int SWR = 0;  // rows per swizzle step (0: no swizzle)
 };
 
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS>
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, int DB, bool TS>
 void launch_conv(const ConvArgs& a, hipStream_t s) {
-    constexpr int MT = WM * TM * 16, NT = WN * TN * 16;
-    const unsigned gx = a.wpt == 1 ? (unsigned)(a.n_win * a.tiles_per_win) : (unsigned)((a.n_win + a.wpt - 1) / a.wpt);
+    constexpr int NT = WN * TN * 16;
+    ConvArgs b = a;
+    b.n_mtiles = a.wpt == 1 ? a.n_win * a.tiles_per_win : (a.n_win + a.wpt - 1) / a.wpt;
+    const unsigned per_xcd = (unsigned)(b.n_mtiles + 7) / 8;   // the kernel's XCD-ordered grid
     hipLaunchKernelGGL((conv_mfma_kernel<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB, TS>),
-                       dim3(gx, (unsigned)(a.C_out / NT)), dim3(64 * WM * WN), 0, s, a);
+                       dim3(8 * per_xcd * (unsigned)(a.C_out / NT)), dim3(64 * WM * WN), 0, s, b);
 }
 
-// TS: allow the tap-shift A-operand reuse where the kernel supports it.
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS = true>
+// DB: the kernel's staging mode (0, 1 or 2; see conv_mfma_kernel).  TS: allow
+// the tap-shift A-operand reuse where the kernel supports it.
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, int DB, bool TS = true>
 ConvCfg make_cfg() {
     ConvCfg c;
     c.fn = launch_conv<P, KW, S, WM, WN, TM, TN, KC, WMAX, DB, TS>;
@@ -89,12 +92,18 @@ Cands cands_lowp(int c_out) {
             return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>(),
                     make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, false, false>()};
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
+                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
+                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
         if (c_out == 64)
             return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, false, false>()};
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
+                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
+                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
+                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>(),
@@ -837,6 +846,29 @@ af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n
 }
 }  // namespace afm
 
+namespace {
+// Switch a conv layer to candidate `idx`: a weight image in that candidate's
+// layout replaces the layer's current one.
+af_status switch_candidate(af_net* net, ConvOp& op, int idx) {
+    ConvOp next = op;
+    next.cand = idx;
+    next.cfg = op.cands[idx];
+    set_tiling(next);
+    std::vector<unsigned char> img = build_image(next, next.cfg, net->prec, net->wfold, net->wscale);
+    void* d_img = nullptr;
+    if (hipMalloc(&d_img, img.size()) != hipSuccess ||
+        hipMemcpy(d_img, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
+        if (d_img) (void)hipFree(d_img);
+        set_error("weight image upload failed");
+        return AF_ENOMEM;
+    }
+    (void)hipFree(op.d_img);
+    next.d_img = d_img;
+    op = next;
+    return AF_OK;
+}
+}  // namespace
+
 extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_t ws_bytes, af_stream stream,
                                      int64_t* n_changed) {
     clear_error();
@@ -910,22 +942,14 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
         }
         if (result != AF_OK) break;
         if (best != op.cand) {
-            ConvOp next = op;
-            next.cand = best;
-            next.cfg = op.cands[best];
-            set_tiling(next);
-            std::vector<unsigned char> img = build_image(next, next.cfg, net->prec, net->wfold, net->wscale);
-            void* d_img = nullptr;
-            if (hipMalloc(&d_img, img.size()) != hipSuccess ||
-                hipMemcpy(d_img, img.data(), img.size(), hipMemcpyHostToDevice) != hipSuccess) {
-                if (d_img) (void)hipFree(d_img);
-                set_error("autotune: weight image upload failed");
-                result = AF_ENOMEM;
+            // the old image may still be read by work queued on another stream
+            if (hipDeviceSynchronize() != hipSuccess) {
+                set_error("autotune: device synchronisation failed");
+                result = AF_EHIP;
                 break;
             }
-            (void)hipFree(op.d_img);
-            next.d_img = d_img;
-            op = next;
+            result = switch_candidate(net, op, best);
+            if (result != AF_OK) break;
             ++changed;
         }
     }
@@ -947,6 +971,22 @@ extern "C" af_status af_net_layer_tile(const af_net* net, int64_t layer, int32_t
     *n_candidates = (int32_t)op.cands.size();
     *chosen = op.cand;
     return AF_OK;
+}
+
+extern "C" af_status af_net_set_layer_tile(af_net* net, int64_t layer, int32_t chosen) {
+    clear_error();
+    AF_CHECK_ARG(net, "net must be non-null");
+    AF_CHECK_ARG(layer >= 1 && layer <= (int64_t)net->ops.size(), "layer must be a conv index in [1, %zu]",
+                 net->ops.size());
+    ConvOp& op = net->ops[layer - 1];
+    AF_CHECK_ARG(chosen >= 0 && chosen < (int32_t)op.cands.size(), "layer %lld has %zu tile candidates",
+                 (long long)layer, op.cands.size());
+    if (chosen == op.cand) return AF_OK;
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    AF_HIP(hipDeviceSynchronize());   // the old image may still be in use
+    return switch_candidate(net, op, chosen);
 }
 
 extern "C" int64_t af_net_n_layers(const af_net* net) { return net ? (int64_t)net->layer_macs.size() : 0; }

@@ -206,6 +206,7 @@ struct ConvArgs {
     int tt;                // output times per window per tile (multiple of 16)
     int tiles_per_win;     // M tiles per window when wpt == 1
     int relu;
+    int n_mtiles;          // M tiles (set by the launcher)
 };
 
 template <int KW, int KC, int MK>
@@ -234,17 +235,23 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, floa
 // K is walked in chunks of KC input channels x all KW taps.  Per chunk the
 // input rows of every window in the tile (the slab, rows t*S - (KW-1)/2 ...)
 // and the chunk's weights are staged in LDS with 16-byte loads; tap j then
-// reads the slab shifted by j rows.  With DB the next chunk is fetched into
-// registers while the current one is multiplied (two LDS buffers).
-// Waves per SIMD the register allocation aims for: three for the small
-// single-buffered 16/8-bit tiles with 16- or 8-byte operands (whose LDS lets
-// three workgroups share a CU), otherwise the compiler's choice.
-template <typename P, int WM, int WN, int TM, int TN, bool DB>
+// reads the slab shifted by j rows.  Staging (DB): 0, one LDS buffer, each
+// chunk fetched and stored between two barriers; 1, two LDS buffers, the next
+// chunk fetched into registers while the current one is multiplied and
+// stored into the other buffer; 2, one LDS buffer, the next chunk fetched
+// into registers during the MFMAs and stored between two barriers.
+// Waves per SIMD the register allocation aims for: for the small 16/8-bit
+// tiles with 16- or 8-byte operands in one LDS buffer (whose LDS lets three
+// workgroups share a CU) three, or two when the next chunk is held in
+// registers; otherwise the compiler's choice.
+template <typename P, int WM, int WN, int TM, int TN, int DB>
 constexpr int conv_waves_per_eu() {
-    return (!DB && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64) ? 3 : 1;
+    return (DB != 1 && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64)
+               ? (DB == 0 ? 3 : 2)
+               : 1;
 }
 
-template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, bool DB, bool TS = true>
+template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, int DB, bool TS = true>
 __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM, TN, DB>()))
     conv_mfma_kernel(ConvArgs a) {
     using Op = typename P::Op;
@@ -278,14 +285,16 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     constexpr int SLAB_ROWS = ROWS_W1 > ROWS_WMAX ? ROWS_W1 : ROWS_WMAX;
     constexpr int SLAB_EL = SLAB_ROWS * PA;
     constexpr int W_EL = KWP * NT * PB;
-    constexpr int NBUF = DB ? 2 : 1;
+    static_assert(DB >= 0 && DB <= 2, "staging mode");
+    constexpr bool LDS2 = DB == 1;   // two LDS buffers
+    constexpr bool PREF = DB != 0;   // next chunk fetched into registers during the MFMAs
+    constexpr int NBUF = LDS2 ? 2 : 1;
     // slab: 16-byte vectors through registers.  Weights (the chunk's LDS image,
-    // padding included): with DB also through registers, loaded at the start
-    // of the chunk before and written to LDS at its end, since a direct
+    // padding included): with PREF also through registers, loaded at the
+    // start of the chunk before and written to LDS at its end, since a direct
     // global->LDS copy in flight makes every LDS read of the current chunk
-    // wait for it (the wait counters cannot tell the two buffers apart);
-    // without DB nothing overlaps, and direct global->LDS copies save the
-    // registers
+    // wait for it (the wait counters cannot tell the buffers apart); without
+    // PREF nothing overlaps, and direct global->LDS copies save the registers
     constexpr int AE = 16 / (int)sizeof(Act);   // activations per 16-byte load
     constexpr int AV_ROW = KC / AE;             // vectors per slab row
     static_assert(KC % AE == 0, "slab rows must be whole 16-byte vectors");
@@ -294,8 +303,8 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     constexpr int W_BYTES = W_EL * OPB;           // one chunk's weight image
     static_assert(W_BYTES % 16 == 0 && (SLAB_EL * OPB) % 16 == 0, "16-byte LDS regions");
     constexpr int WV = W_BYTES / 16;              // 16-byte vectors of the weight image
-    constexpr int RW = DB ? (WV + NTH - 1) / NTH : 1;  // weight vectors per thread (DB)
-    constexpr int W_INST = (W_BYTES + 1023) / 1024;    // wave-wide 1 KB copies (no DB)
+    constexpr int RW = PREF ? (WV + NTH - 1) / NTH : 1;  // weight vectors per thread (PREF)
+    constexpr int W_INST = (W_BYTES + 1023) / 1024;      // wave-wide 1 KB copies (no PREF)
     constexpr int NWAVES = WM * WN;
     // the epilogue reuses the same LDS for the FP32 output tile [MT][NT + 4]
     constexpr int EPITCH = NT + 4;
@@ -313,15 +322,25 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     const int r16 = lane & 15;   // row (A) / column (B) inside a 16x16 tile
     const int wpt = a.wpt, tt = a.tt;
     const int srows = (tt - 1) * S + KWP;   // slab rows per window
+    // Workgroup order: consecutive workgroups go to the 8 XCDs in turn.  Each
+    // XCD takes a contiguous range of M tiles and, for each, all N tiles one
+    // after another, so that the N tiles reading one input slab run together
+    // and find it in that XCD's L2.  The grid is rounded up to whole ranges;
+    // the surplus workgroups return at once.
+    const int n_nt = a.C_out / NT;
+    const int per_xcd = (a.n_mtiles + 7) >> 3;
+    const int kx = (int)(blockIdx.x >> 3);
+    const int mtile = (int)(blockIdx.x & 7) * per_xcd + kx / n_nt;
+    const int nt = kx % n_nt;
+    if (mtile >= a.n_mtiles) return;
     int win0, t0;
     if (wpt == 1) {
-        win0 = blockIdx.x / a.tiles_per_win;
-        t0 = (blockIdx.x % a.tiles_per_win) * tt;
+        win0 = mtile / a.tiles_per_win;
+        t0 = (mtile % a.tiles_per_win) * tt;
     } else {
-        win0 = blockIdx.x * wpt;
+        win0 = mtile * wpt;
         t0 = 0;
     }
-    const int nt = blockIdx.y;
     const int n0 = nt * NT;
     const int n_chunks = a.C_in / KC;
     const Act* in = (const Act*)a.in;
@@ -394,7 +413,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         }                                                                                          \
     }
 #define AFM_WLOAD(RWV, CC, BUF)                                                                    \
-    if constexpr (DB) {                                                                            \
+    if constexpr (PREF) {                                                                          \
         const uint4* src_ = (const uint4*)(wimg + (size_t)(CC) * W_BYTES);                        \
         _Pragma("unroll") for (int i = 0; i < RW; ++i) {                                          \
             const int u = tid + i * NTH;                                                           \
@@ -413,7 +432,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #define AFM_STASH(RWV, BUF)                                                                        \
     {                                                                                              \
         Op* slab_ = smem + (BUF) * (SLAB_EL + W_EL);                                               \
-        if constexpr (DB) {                                                                        \
+        if constexpr (PREF) {                                                                      \
             uint4* wdst_ = (uint4*)(slab_ + SLAB_EL);                                              \
             _Pragma("unroll") for (int i = 0; i < RW; ++i) {                                      \
                 const int u = tid + i * NTH;                                                       \
@@ -450,9 +469,9 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     for (int cc = 0; cc < n_chunks; ++cc) {
-        const int buf = DB ? (cc & 1) : 0;
-        u4v rw[RW];  // the next chunk's weights (DB), loaded now, stored to LDS after the MFMAs
-        if (DB && cc + 1 < n_chunks) {
+        const int buf = LDS2 ? (cc & 1) : 0;
+        u4v rw[RW];  // the next chunk's weights (PREF), loaded now, stored to LDS after the MFMAs
+        if (PREF && cc + 1 < n_chunks) {
             AFM_FETCH(cc + 1)
             AFM_WLOAD(rw, cc + 1, buf ^ 1)
         }
@@ -543,10 +562,17 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #pragma unroll
                 for (int jn = 0; jn < TN; ++jn) mfma_step<P>(acc[i][jn], ab[i], bb[jn]);
         }
-        if (DB) {
+        if (LDS2) {
             if (cc + 1 < n_chunks) AFM_STASH(rw, buf ^ 1)
             __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
+        } else if (PREF) {
+            if (cc + 1 < n_chunks) {
+                __syncthreads();   // every wave is done reading this chunk
+                AFM_STASH(rw, 0)
+                __builtin_amdgcn_s_waitcnt(0);
+                __syncthreads();
+            }
         } else if (cc + 1 < n_chunks) {
             __syncthreads();
             AFM_FETCH(cc + 1)

@@ -167,6 +167,34 @@ def test_autotune_keeps_logits(prec):
     np.testing.assert_allclose(after, before, atol=1e-5 if prec == "f32" else 2e-3)
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16", "bf16f", "fp8"])
+def test_every_tile_candidate_same_logits(prec):
+    # every tile shape the autotuner may choose, layer by layer, gives the
+    # logits of the default shape bit for bit (the k summation order does not
+    # depend on the tiling)
+    P = need_gpu()
+    banner(f"tile candidates resnet {prec}")
+    params = make_params(RESNET_ARCH, seed=27)
+    y = dev(series(3072 + 128 * 5, seed=28))
+    net = P.Net(RESNET_ARCH, params, prec)
+    ref = net.score_windows(y, 128, batch=3).cpu().numpy()
+    tried = 0
+    for layer, (_, _, n_cand, chosen) in enumerate(net.tiles(), start=1):
+        for c in range(n_cand):
+            if c == chosen:
+                continue
+            net.set_tile(layer, c)
+            got = net.score_windows(y, 128, batch=3).cpu().numpy()
+            assert np.array_equal(got, ref), f"layer {layer} candidate {c}: max|d| {np.abs(got - ref).max():.3e}"
+            tried += 1
+        net.set_tile(layer, chosen)
+    print(f"{prec}: {tried} alternative tiles, all identical")
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        net.set_tile(1, net.tiles()[0][2])
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        net.set_tile(0, 0)
+
+
 SHALLOW = [NetArch("shallow32", 2, 32, 7, 2, True, (32,), (1,)),
            NetArch("shallow64", 2, 32, 7, 2, True, (32, 64), (1, 1)),
            NetArch("shallow128", 2, 32, 7, 2, True, (32, 64, 128), (1, 1, 1))]
