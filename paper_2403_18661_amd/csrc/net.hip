@@ -49,7 +49,7 @@ ConvCfg make_cfg() {
     constexpr int OPB = (int)sizeof(typename P::Op);
     c.PB = OPB == 4 ? KC + 4 : (P::KL == 32 ? KC + 16 : KC);   // these three must match the kernel's PB, KL, SWR
     c.KL = P::KL;
-    c.SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
+    c.SWR = weight_swizzle_rows<OPB, KC>();
     return c;
 }
 
@@ -80,6 +80,13 @@ Cands cands_f32(int c_out) {
 // BF16 / FP8: tiles of up to 192 rows (two short windows per tile) x 128/64
 // columns, 256 x 32/16 for the narrow layers, double-buffered LDS except where
 // the stride-2 slab would not fit twice.
+// 384 x 64 tile of eight waves stacked along M (48 x 64 each), two LDS
+// buffers: one workgroup per CU whose next chunk lands while it multiplies
+template <typename P, int KW, int S, int KC>
+void add_tall_db(Cands& c) {
+    if constexpr (KW == 7 && S == 1 && KC == 32) c.push_back(make_cfg<P, 7, 1, 8, 1, 3, 4, 32, 4, 1, false>());
+}
+
 template <typename P, int KW, int S, int KC>
 Cands cands_lowp(int c_out) {
     if constexpr (KC == 16) {
@@ -88,22 +95,28 @@ Cands cands_lowp(int c_out) {
         return {};
     } else {
         constexpr bool DB_WIDE = !(KW == 7 && S == 2);
-        if (c_out % 128 == 0)
-            return {make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
+        if (c_out % 128 == 0) {
+            Cands c{make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>(),
                     make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
                     make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
                     make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
-        if (c_out == 64)
-            return {make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
+            add_tall_db<P, KW, S, KC>(c);
+            return c;
+        }
+        if (c_out == 64) {
+            Cands c{make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
                     make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
                     make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
                     make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
+            add_tall_db<P, KW, S, KC>(c);
+            return c;
+        }
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>(),

@@ -209,6 +209,26 @@ struct ConvArgs {
     int n_mtiles;          // M tiles (set by the launcher)
 };
 
+// LDS layout of the 16-byte operand reads of gfx950 (ds_read_b128 by 64
+// lanes, 16 rows x 4 units of 16 bytes): rows 96 or 160 bytes apart, or
+// 64-byte rows whose units are XOR-swizzled by (row / 2) & 3, are read
+// without bank conflicts; 64-, 80-, 112- and 144-byte pitches and a row / 4
+// swizzle conflict two ways (measured).
+// Slab row pitch in elements: 32-channel 16-bit chunks get 96-byte rows,
+// other chunks 16 bytes of padding.
+template <int OPB, int KC>
+constexpr int slab_pitch() {
+    return (OPB == 2 && KC == 32) ? KC + 16 : KC + 16 / OPB;
+}
+// Rows per step of the XOR swizzle of unpadded 16/8-bit weight rows (0: the
+// FP32 rows are padded instead).
+template <int OPB, int KC>
+constexpr int weight_swizzle_rows() {
+    if constexpr (OPB == 4) return 0;
+    else if constexpr (OPB == 2 && KC == 32) return 2;
+    else return 256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1;
+}
+
 template <int KW, int KC, int MK>
 struct ChunkGeom {
     static constexpr int KCH = KW * KC;
@@ -267,14 +287,14 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     static_assert(KPAD % KC == 0, "chunk padding must be whole taps");
     static_assert(KC % KL == 0, "lane k-run must stay inside one tap");
     constexpr int OPB = (int)sizeof(Op);
-    constexpr int PA = KC + 16 / OPB;           // slab row pitch in elements (16 B of padding)
+    constexpr int PA = slab_pitch<OPB, KC>();   // slab row pitch in elements
     // weight row pitch: FP32 lanes read 4 B (pad 4); 32-byte FP8 lane reads (pad 16 B)
     constexpr int PB = OPB == 4 ? KC + 4 : (KL == 32 ? KC + 16 : KC);
     // BF16/FP8 weight rows are not padded; instead the KL-element units of row
     // r are XOR-swizzled by (r / SWR) & (KC/KL - 1), so that the 16 rows one
     // MFMA operand read touches fall in distinct LDS banks
     constexpr int SWU = KC / KL;                                    // units per row
-    constexpr int SWR = OPB == 4 ? 0 : (256 / (KC * OPB) > 0 ? 256 / (KC * OPB) : 1);
+    constexpr int SWR = weight_swizzle_rows<OPB, KC>();
     // tap-shift reuse of the A operand (see the k-loop)
     constexpr bool SHIFT = TS && S == 1 && KW > 1 && MK == KC && KPAD == KW * KC && OPB <= 2 && KL == 8;
     constexpr int PAD = (KW - 1) / 2;
