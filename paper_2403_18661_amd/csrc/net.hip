@@ -77,16 +77,11 @@ Cands cands_f32(int c_out) {
     return {};
 }
 
-// BF16 / FP8: tiles of up to 192 rows (two short windows per tile) x 128/64
-// columns, 256 x 32/16 for the narrow layers, double-buffered LDS except where
-// the stride-2 slab would not fit twice.
-// 384 x 64 tile of eight waves stacked along M (48 x 64 each), two LDS
-// buffers: one workgroup per CU whose next chunk lands while it multiplies
-template <typename P, int KW, int S, int KC>
-void add_tall_db(Cands& c) {
-    if constexpr (KW == 7 && S == 1 && KC == 32) c.push_back(make_cfg<P, 7, 1, 8, 1, 3, 4, 32, 4, 1, false>());
-}
-
+// BF16 / FP8: a 192 x 64 tile of four waves stacked along M (48 x 64 each)
+// in one LDS buffer (three workgroups per CU), the same with the next chunk
+// prefetched into registers, the 192 x 64 tile of 2 x 2 waves, and a
+// double-buffered 96-row tile (the 1x1 projections); 256 x 32/16 for the
+// narrow layers.  The first is the default.
 template <typename P, int KW, int S, int KC>
 Cands cands_lowp(int c_out) {
     if constexpr (KC == 16) {
@@ -94,29 +89,10 @@ Cands cands_lowp(int c_out) {
             return {make_cfg<P, 7, 1, 4, 1, 4, 1, 16, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 1, 16, 1, true>()};
         return {};
     } else {
-        constexpr bool DB_WIDE = !(KW == 7 && S == 2);
-        if (c_out % 128 == 0) {
-            Cands c{make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE>(), make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, true>(),
-                    make_cfg<P, KW, S, 1, 4, 12, 2, KC, 2, DB_WIDE>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 4, KC, 2, DB_WIDE, false>(),
+        if (c_out % 64 == 0)
+            return {make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(), make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
-                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
-                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
-            add_tall_db<P, KW, S, KC>(c);
-            return c;
-        }
-        if (c_out == 64) {
-            Cands c{make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true>(), make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, true>(),
-                    make_cfg<P, KW, S, 1, 4, 12, 1, KC, 2, true>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, true, false>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
-                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(),
-                    make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 2, false>(),
-                    make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>()};
-            add_tall_db<P, KW, S, KC>(c);
-            return c;
-        }
+                    c_out % 128 == 0 ? make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, 1>() : make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, 1>()};
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>(),
@@ -177,9 +153,13 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int ro
         if (s == 1 && c_out == 32) {
             c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 2, 2, 32, 1, false, false>());
             c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 4, 2, 32, 1, false, false>());
-        } else if (c_out % 64 == 0) {
-            if (s == 1) c.push_back(make_cfg<PFP8, 7, 1, 2, 2, 6, 2, 32, 2, false, false>());
-            if (s == 2) c.push_back(make_cfg<PFP8, 7, 2, 2, 2, 6, 2, 32, 2, false, false>());
+        } else if (c_out % 64 == 0 && s == 1) {
+            c.push_back(make_cfg<PFP8, 7, 1, 2, 2, 6, 2, 32, 2, 0, false>());
+            c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 3, 4, 32, 2, 0, false>());
+            c.push_back(make_cfg<PFP8, 7, 1, 4, 1, 3, 4, 32, 2, 2, false>());
+        } else if (c_out % 64 == 0 && s == 2) {
+            c.push_back(make_cfg<PFP8, 7, 2, 2, 2, 6, 2, 32, 2, 0, false>());
+            c.push_back(make_cfg<PFP8, 7, 2, 4, 1, 3, 4, 32, 2, 0, false>());
         }
         return c;
     }

@@ -260,15 +260,17 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, floa
 // chunk fetched into registers while the current one is multiplied and
 // stored into the other buffer; 2, one LDS buffer, the next chunk fetched
 // into registers during the MFMAs and stored between two barriers.
-// Waves per SIMD the register allocation aims for: for the small 16/8-bit
-// tiles with 16- or 8-byte operands in one LDS buffer (whose LDS lets three
-// workgroups share a CU) three, or two when the next chunk is held in
-// registers; otherwise the compiler's choice.
+// Waves per SIMD the register allocation aims for: three for the small
+// 16/8-bit tiles with 16- or 8-byte operands in one LDS buffer (whose LDS
+// lets three workgroups share a CU), two when such a tile holds the next
+// chunk's FP32 activations in registers (three would spill); otherwise the
+// compiler's choice.
 template <typename P, int WM, int WN, int TM, int TN, int DB>
 constexpr int conv_waves_per_eu() {
-    return (DB != 1 && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64)
-               ? (DB == 0 ? 3 : 2)
-               : 1;
+    if constexpr (DB != 1 && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64)
+        return (DB == 2 && sizeof(typename P::Act) == 4) ? 2 : 3;
+    else
+        return 1;
 }
 
 template <typename P, int KW, int S, int WM, int WN, int TM, int TN, int KC, int WMAX, int DB, bool TS = true>
