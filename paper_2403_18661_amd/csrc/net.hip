@@ -89,10 +89,19 @@ Cands cands_lowp(int c_out) {
             return {make_cfg<P, 7, 1, 4, 1, 4, 1, 16, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 1, 16, 1, true>()};
         return {};
     } else {
-        if (c_out % 64 == 0)
-            return {make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(), make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>(),
+        if (c_out % 64 == 0) {
+            Cands c{make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 0, false>(), make_cfg<P, KW, S, 4, 1, 3, 4, KC, 2, 2, false>(),
                     make_cfg<P, KW, S, 2, 2, 6, 2, KC, 2, 0, false>(),
                     c_out % 128 == 0 ? make_cfg<P, KW, S, 2, 2, 3, 4, KC, 1, 1>() : make_cfg<P, KW, S, 2, 2, 3, 2, KC, 1, 1>()};
+            // 384 x 64 of eight waves stacked along M: half the weight bytes
+            // per MAC of the 192-row tiles (stride-1 k7 layers with 16-byte
+            // operands; the FP32-in, FP32-out form would not fit the 128
+            // registers of four waves per SIMD)
+            constexpr bool f32_io = sizeof(typename P::Act) == 4 && sizeof(typename P::OAct) == 4;
+            if constexpr (KW == 7 && S == 1 && P::KL == 8 && !P::kFP8 && !f32_io)
+                c.push_back(make_cfg<P, 7, 1, 8, 1, 3, 4, KC, 4, 0, false>());
+            return c;
+        }
         if constexpr (KW == 7 && S == 1) {
             if (c_out == 32)
                 return {make_cfg<P, 7, 1, 4, 1, 4, 2, KC, 1, true>(), make_cfg<P, 7, 1, 4, 1, 2, 2, KC, 1, true>(),

@@ -263,11 +263,14 @@ __device__ __forceinline__ uint32_t pack_e4m3x4(uint32_t lo2, uint32_t hi2, floa
 // Waves per SIMD the register allocation aims for: three for the small
 // 16/8-bit tiles with 16- or 8-byte operands in one LDS buffer (whose LDS
 // lets three workgroups share a CU), two when such a tile holds the next
-// chunk's FP32 activations in registers (three would spill); otherwise the
-// compiler's choice.
+// chunk's FP32 activations in registers (three would spill); four for the
+// eight-wave 16/8-bit tiles in one buffer (two workgroups per CU);
+// otherwise the compiler's choice.
 template <typename P, int WM, int WN, int TM, int TN, int DB>
 constexpr int conv_waves_per_eu() {
-    if constexpr (DB != 1 && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64)
+    if constexpr (DB == 0 && WM * WN == 8 && sizeof(typename P::Op) <= 2 && P::KL <= 8)
+        return 4;
+    else if constexpr (DB != 1 && sizeof(typename P::Op) <= 2 && P::KL <= 8 && WM * TM * WN * TN * 256 <= 192 * 64)
         return (DB == 2 && sizeof(typename P::Act) == 4) ? 2 : 3;
     else
         return 1;
@@ -328,10 +331,15 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     constexpr int RW = PREF ? (WV + NTH - 1) / NTH : 1;  // weight vectors per thread (PREF)
     constexpr int W_INST = (W_BYTES + 1023) / 1024;      // wave-wide 1 KB copies (no PREF)
     constexpr int NWAVES = WM * WN;
-    // the epilogue reuses the same LDS for the FP32 output tile [MT][NT + 4]
+    // the epilogue reuses the same LDS for the FP32 output tile [MT][NT + 4],
+    // in EPH row phases of MTP rows: tall tiles of waves stacked along M
+    // stage half of their rows at a time so that the epilogue does not need
+    // more LDS than the main loop
     constexpr int EPITCH = NT + 4;
+    constexpr int EPH = (WN == 1 && WM % 2 == 0 && MT >= 384) ? 2 : 1;
+    constexpr int MTP = MT / EPH;
     constexpr int BUF_BYTES = NBUF * (SLAB_EL + W_EL) * OPB;
-    constexpr int EPI_BYTES = MT * EPITCH * 4;
+    constexpr int EPI_BYTES = MTP * EPITCH * 4;
     constexpr int SMEM_BYTES = BUF_BYTES > EPI_BYTES ? BUF_BYTES : EPI_BYTES;
     __shared__ __attribute__((aligned(16))) unsigned char smem_raw[SMEM_BYTES];
     Op* smem = (Op*)smem_raw;
@@ -610,27 +618,13 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 
     // epilogue: the accumulators go through LDS so that bias, dequant,
     // residual, ReLU, rounding and the stores run on 16-byte row vectors
-    __syncthreads();
     float* et = (float*)smem_raw;
-#pragma unroll
-    for (int i = 0; i < TM; ++i)
-#pragma unroll
-        for (int jn = 0; jn < TN; ++jn)
-#pragma unroll
-            for (int r = 0; r < 4; ++r)
-                et[((wm * TM + i) * 16 + g * 4 + r) * EPITCH + (wn * TN + jn) * 16 + r16] = acc[i][jn][r];
-    __syncthreads();
     constexpr int VE = 16 / (int)sizeof(OAct);   // outputs per 16-byte vector
     constexpr int VPR = NT / VE;                // vectors per tile row
-    constexpr int EPI_IT = (MT * VPR + NTH - 1) / NTH;
+    constexpr int EPI_IT = (MTP * VPR + NTH - 1) / NTH;
     float vmax[WMAX];
 #pragma unroll
     for (int u = 0; u < WMAX; ++u) vmax[u] = 0.f;
-    // all residual loads first (a thread reads and later writes the same
-    // elements, so this also holds when the output overwrites the residual)
-    uint4 rres[EPI_IT];
-    size_t ooff[EPI_IT];
-    bool oval[EPI_IT];
     // NTH is a multiple of VPR, so a thread's columns are the same in every
     // iteration: its bias (and FP8 weight scales) are loaded once
     static_assert(NTH % VPR == 0, "epilogue columns must not depend on the iteration");
@@ -642,12 +636,30 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         scol[e] = P::kFP8 ? a.wscale[n0 + col_t + e] : 1.f;
     }
 #pragma unroll
+    for (int ph = 0; ph < EPH; ++ph) {
+    __syncthreads();
+    if (EPH == 1 || wm / (WM / EPH) == ph) {
+#pragma unroll
+        for (int i = 0; i < TM; ++i)
+#pragma unroll
+            for (int jn = 0; jn < TN; ++jn)
+#pragma unroll
+                for (int r = 0; r < 4; ++r)
+                    et[((wm * TM + i) * 16 + g * 4 + r - ph * MTP) * EPITCH + (wn * TN + jn) * 16 + r16] = acc[i][jn][r];
+    }
+    __syncthreads();
+    // all residual loads first (a thread reads and later writes the same
+    // elements, so this also holds when the output overwrites the residual)
+    uint4 rres[EPI_IT];
+    size_t ooff[EPI_IT];
+    bool oval[EPI_IT];
+#pragma unroll
     for (int it = 0; it < EPI_IT; ++it) {
         const int v = tid + it * NTH;
-        const int row = v / VPR, col = (v % VPR) * VE;
+        const int row = ph * MTP + v / VPR, col = (v % VPR) * VE;
         const int w = row / tt;
         const int t = t0 + row % tt;
-        oval[it] = v < MT * VPR && win0 + w < a.n_win && t < a.L_out;
+        oval[it] = v < MTP * VPR && win0 + w < a.n_win && t < a.L_out;
         ooff[it] = ((size_t)(win0 + w) * a.L_out + t) * a.C_out + n0 + col;
         rres[it] = make_uint4(0u, 0u, 0u, 0u);
         if (a.res && oval[it]) rres[it] = *(const uint4*)((const OAct*)a.res + ooff[it]);
@@ -662,20 +674,20 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #pragma unroll
         for (int it = 0; it < EPI_IT; ++it) {
             const int v = tid + it * NTH;
-            const int row = (v < MT * VPR ? v : 0) / VPR;
+            const int lrow = (v < MTP * VPR ? v : 0) / VPR;
 #pragma unroll
-            for (int e = 0; e < VE; ++e) xt[it][e] = et[row * EPITCH + col_t + e];
+            for (int e = 0; e < VE; ++e) xt[it][e] = et[lrow * EPITCH + col_t + e];
         }
     }
 #pragma unroll
     for (int it = 0; it < EPI_IT; ++it) {
         if (!oval[it]) continue;
         const int v = tid + it * NTH;
-        const int row = v / VPR;
-        const int w = row / tt;
+        const int lrow = v / VPR;
+        const int w = (ph * MTP + lrow) / tt;
         float x[VE];
 #pragma unroll
-        for (int e = 0; e < VE; ++e) x[e] = XPRE ? xt[XPRE ? it : 0][e] : et[row * EPITCH + col_t + e];
+        for (int e = 0; e < VE; ++e) x[e] = XPRE ? xt[XPRE ? it : 0][e] : et[lrow * EPITCH + col_t + e];
         float sa = 1.f;
         if constexpr (P::kFP8) {
             sa = s_a[0];
@@ -724,6 +736,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
                 if (w == u) vmax[u] = fmaxf(vmax[u], m);
         }
     }
+    }   // epilogue phases
     if constexpr (P::kFP8) {
         if (a.amax_out) {
 #pragma unroll
