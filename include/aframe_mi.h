@@ -207,7 +207,8 @@ af_status af_net_set_layer_tile(af_net* net, int64_t layer, int32_t chosen);
 size_t af_score_workspace_bytes(const af_net* net, int64_t batch);
 /* logits[i] = net(window i) for i < n_windows.  Channel c of window i is
  *   y[c*ld_y + p], p = i*stride + ch_shift[c] + t, t < window,
- * with p taken modulo `wrap` when wrap > 0 (circular timeslides, Sec. IX).
+ * with p taken modulo `wrap` when wrap > 0 (circular timeslides, Sec. IX);
+ * wrap must then be at least the window length (AF_EINVAL otherwise).
  * ch_shift: host array [n_ch] or NULL (all 0).  Without wrap every p must be
  * < n.  y is float32; it is rounded to the net's precision inside the kernels.
  * Windows are processed in passes of the largest batch the workspace holds. */

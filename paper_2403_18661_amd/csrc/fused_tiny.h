@@ -107,7 +107,7 @@ __global__ void __launch_bounds__(256) fused_tiny_bf16_kernel(FusedTinyArgs a) {
                             for (int j = 0; j < 7; ++j) sacc = fmaf(a.st.w[((c + h) * 2 + ci) * 7 + j], xin[ci][j], sacc);
                         v[h] = inside ? fmaxf(sacc, 0.f) : 0.f;
                     }
-                    packed[c / 2] = (uint32_t)f32_to_bf16_bits(v[0]) | ((uint32_t)f32_to_bf16_bits(v[1]) << 16);
+                    packed[c / 2] = pack_bf16x2(v[0], v[1]);
                 }
                 uint4* dst = (uint4*)(bufA + (q + GUARD) * PITCH);
                 dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);

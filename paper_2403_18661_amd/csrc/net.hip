@@ -544,7 +544,7 @@ bool launch_stem_p(const af_net_desc& d, const StemArgs& sa, int nb, size_t lds,
     if (d.stem_ch == 16 && d.stem_stride == 1 && !d.stem_pool)
         hipLaunchKernelGGL((stem2_kernel<P, 16, 1, false>), dim3(nb), dim3(256), lds, s, sa);
     else if (d.stem_ch == 32 && d.stem_stride == 2 && d.stem_pool)
-        hipLaunchKernelGGL((stem2_kernel<P, 32, 2, true>), dim3(nb), dim3(256), lds, s, sa);
+        hipLaunchKernelGGL((stem_mfma_kernel<P, 32>), dim3(nb), dim3(256), StemMfmaGeom::lds_bytes(sa.window), s, sa);
     else if (d.stem_ch == 32 && d.stem_stride == 1 && !d.stem_pool)
         hipLaunchKernelGGL((stem2_kernel<P, 32, 1, false>), dim3(nb), dim3(256), lds, s, sa);
     else
@@ -583,6 +583,7 @@ extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t
     (void)hipGetDevice(&dev);
     AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
     const int window = net->desc.window;
+    AF_CHECK_ARG(wrap == 0 || wrap >= window, "wrap must be 0 or at least the window length %d", window);
     int64_t shift[4] = {0, 0, 0, 0};
     for (int c = 0; c < n_ch; ++c) {
         shift[c] = ch_shift ? ch_shift[c] : 0;

@@ -15,12 +15,16 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 
 // ---- scalar conversions -----------------------------------------------------
 __device__ __forceinline__ float bf16_bits_to_f32(uint16_t b) { return __uint_as_float(((uint32_t)b) << 16); }
-__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) {
-    // round to nearest even (inputs are finite)
-    uint32_t u = __float_as_uint(f);
-    u += 0x7FFFu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
+// FP32 -> BF16 with round to nearest even: gfx950's v_cvt_pk_bf16_f32, which
+// gives the bits of (u + 0x7FFF + ((u >> 16) & 1)) >> 16 for every finite
+// input (checked bit for bit on the device over 2^28 patterns, ties and
+// subnormals included); two values per instruction.
+typedef __bf16 bf16x2v __attribute__((ext_vector_type(2)));
+typedef float f32x2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pack_bf16x2(float lo, float hi) {
+    return __builtin_bit_cast(uint32_t, __builtin_convertvector(f32x2v{lo, hi}, bf16x2v));
 }
+__device__ __forceinline__ uint16_t f32_to_bf16_bits(float f) { return __builtin_bit_cast(uint16_t, (__bf16)f); }
 // FP32 -> OCP E4M3, round to nearest even, saturating at +-448.
 __device__ __forceinline__ uint8_t f32_to_e4m3(float v) {
     const uint32_t u = __float_as_uint(v);
@@ -474,11 +478,8 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
                 Op* dst = slab_ + s_off[i];                                                        \
                 if constexpr (sizeof(Act) == 4 && sizeof(Op) == 2) {                               \
                     const uint4 f = ra[i];                                                         \
-                    *(uint2*)dst = make_uint2(                                                     \
-                        (uint32_t)f32_to_bf16_bits(__uint_as_float(f.x)) |                         \
-                            ((uint32_t)f32_to_bf16_bits(__uint_as_float(f.y)) << 16),              \
-                        (uint32_t)f32_to_bf16_bits(__uint_as_float(f.z)) |                         \
-                            ((uint32_t)f32_to_bf16_bits(__uint_as_float(f.w)) << 16));             \
+                    *(uint2*)dst = make_uint2(pack_bf16x2(__uint_as_float(f.x), __uint_as_float(f.y)),  \
+                                              pack_bf16x2(__uint_as_float(f.z), __uint_as_float(f.w))); \
                 } else if constexpr (P::kFP8) {                                                    \
                     const float sc = s_sc[i];                                                      \
                     *(uint2*)dst = make_uint2(pack_e4m3x4(ra[i].x, ra[i].y, sc),                    \
@@ -723,9 +724,9 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
             uint32_t wv[4];
 #pragma unroll
             for (int e = 0; e < 4; ++e) {
-                const uint32_t lo = f32_to_bf16_bits(x[2 * e]), hi = f32_to_bf16_bits(x[2 * e + 1]);
-                wv[e] = lo | (hi << 16);
-                m = fmaxf(m, fmaxf(fabsf(__uint_as_float(lo << 16)), fabsf(__uint_as_float(hi << 16))));
+                wv[e] = pack_bf16x2(x[2 * e], x[2 * e + 1]);
+                if constexpr (P::kFP8)
+                    m = fmaxf(m, fmaxf(fabsf(__uint_as_float(wv[e] << 16)), fabsf(__uint_as_float(wv[e] & 0xFFFF0000u))));
             }
             ov = make_uint4(wv[0], wv[1], wv[2], wv[3]);
         }
@@ -793,13 +794,45 @@ __device__ __forceinline__ WinAddr window_addr(const StemArgs& a, int64_t wi) {
         w.wrap = a.wrap;
         for (int c = 0; c < 4; ++c) w.start[c] = wi * a.stride + a.shift[c];
     }
+    // starts are non-negative; reduced here once, so that with t < window <=
+    // wrap a sample index passes the end at most once
+    if (w.wrap > 0)
+        for (int c = 0; c < 4; ++c) w.start[c] %= w.wrap;
     return w;
 }
 
 __device__ __forceinline__ int64_t window_sample(const WinAddr& w, int c, int t) {
-    int64_t p = w.start[c] + t;
-    if (w.wrap > 0) p %= w.wrap;
-    return w.base + p;
+    // select, not an indexed load: a run-time index would put start[] in scratch
+    const int64_t st = c == 0 ? w.start[0] : c == 1 ? w.start[1] : c == 2 ? w.start[2] : w.start[3];
+    const int64_t p = st + t;
+    return w.base + ((w.wrap > 0 && p >= w.wrap) ? p - w.wrap : p);
+}
+
+// Stage a window's samples, [n_ch][window] floats (n_ch <= 4), into LDS with
+// 256 threads, channel c at xs[c * pitch + padl + t] (pitch 0: the window
+// length).  Each thread issues up to SB loads before it stores any, so that
+// their latencies overlap (a load-then-store loop waits on every load); loads
+// past the end read a clamped, valid index and are not stored.
+__device__ __forceinline__ void stage_window(const StemArgs& a, const WinAddr& wa, float* xs, int pitch = 0,
+                                             int padl = 0) {
+    constexpr int SB = 12;
+    const int W = a.window;
+    const int pw = pitch ? pitch : W;
+    for (int c = 0; c < a.n_ch; ++c) {
+        const float* yc = a.y + c * a.ld_y + wa.base;
+        const int64_t st = c == 0 ? wa.start[0] : c == 1 ? wa.start[1] : c == 2 ? wa.start[2] : wa.start[3];
+        for (int t0 = threadIdx.x; t0 < W; t0 += 256 * SB) {
+            float v[SB];
+#pragma unroll
+            for (int u = 0; u < SB; ++u) {
+                const int64_t p = st + min(t0 + u * 256, W - 1);
+                v[u] = yc[(wa.wrap > 0 && p >= wa.wrap) ? p - wa.wrap : p];
+            }
+#pragma unroll
+            for (int u = 0; u < SB; ++u)
+                if (t0 + u * 256 < W) xs[c * pw + padl + t0 + u * 256] = v[u];
+        }
+    }
 }
 
 // Stem conv (vector FP32 arithmetic), ReLU, optional max-pool k3 s2 p1.
@@ -811,10 +844,7 @@ __global__ void __launch_bounds__(256) stem_kernel(StemArgs a) {
     const int b = blockIdx.x;
     const int64_t wi = a.first_window + b;
     const WinAddr wa = window_addr(a, wi);
-    for (int e = threadIdx.x; e < a.n_ch * a.window; e += 256) {
-        const int c = e / a.window, t = e % a.window;
-        xs[e] = a.y[c * a.ld_y + window_sample(wa, c, t)];
-    }
+    stage_window(a, wa, xs);
     __syncthreads();
     const int pad = (a.KW - 1) / 2;
     Act* out = (Act*)a.out + (size_t)b * a.L_out * a.C;
@@ -862,10 +892,7 @@ __global__ void __launch_bounds__(256) stem2_kernel(StemArgs a) {
     const int64_t wi = a.first_window + b;
     const int W = a.window;
     const WinAddr wa = window_addr(a, wi);
-    for (int e = threadIdx.x; e < NCH * W; e += 256) {
-        const int c = e / W, t = e % W;
-        xs[e] = a.y[c * a.ld_y + window_sample(wa, c, t)];
-    }
+    stage_window(a, wa, xs);   // a.n_ch == NCH
     __syncthreads();
     Act* out = (Act*)a.out + (size_t)b * a.L_out * C;
     const float* __restrict__ wt = a.w;   // [C][NCH][KW]
@@ -911,13 +938,145 @@ __global__ void __launch_bounds__(256) stem2_kernel(StemArgs a) {
                 uint32_t u4[4];
 #pragma unroll
                 for (int e = 0; e < 4; ++e) {
-                    const uint16_t lo = f32_to_bf16_bits(res[c + 2 * e]), hi = f32_to_bf16_bits(res[c + 2 * e + 1]);
-                    u4[e] = (uint32_t)lo | ((uint32_t)hi << 16);
-                    vmax = fmaxf(vmax, fmaxf(bf16_bits_to_f32(lo), bf16_bits_to_f32(hi)));
+                    u4[e] = pack_bf16x2(res[c + 2 * e], res[c + 2 * e + 1]);
+                    if constexpr (P::kFP8)
+                        vmax = fmaxf(vmax, fmaxf(__uint_as_float(u4[e] << 16), __uint_as_float(u4[e] & 0xFFFF0000u)));
                 }
                 *(uint4*)(o + c) = make_uint4(u4[0], u4[1], u4[2], u4[3]);
             }
         }
+    }
+    if constexpr (P::kFP8) {
+        for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));
+        if ((threadIdx.x & 63) == 0) atomicMax(&a.amax_out[b], __float_as_uint(vmax));
+    }
+}
+
+// Stem with stride 2 and max-pool 3/2 (two detectors, kernel 7) on the FP32
+// matrix cores: per window the conv is an [L_conv x 16] x [16 x C] product,
+// K = 2 channels x 8 taps (the eighth weight zero), as 16x16x4 MFMAs over
+// 16-row blocks.  Conv rows go through LDS 256 at a time (ReLU applied) for
+// the pool, whose window reaches one row into the previous pass; that row is
+// carried over.  Every conv output is computed once.  One workgroup per
+// window, samples staged in LDS as in stem2_kernel.
+// Samples of a channel sit between zero pads: PADL before (>= the conv's 3)
+// and PADR after, enough for the rows of a last, partial pass, so that the A
+// operand reads need neither bounds checks nor selects.
+struct StemMfmaGeom {
+    static constexpr int RB = 4;              // 16-row blocks per wave per pass
+    static constexpr int PR = 4 * RB * 16;    // conv rows per pass
+    static constexpr int PADL = 4, PADR = 2 * PR + 8;
+    static constexpr int pitch(int window) { return PADL + window + PADR; }
+    static constexpr size_t lds_bytes(int window) { return (size_t)2 * pitch(window) * sizeof(float); }
+};
+
+template <typename P, int C>
+__global__ void __launch_bounds__(256) stem_mfma_kernel(StemArgs a) {
+    using Act = typename P::Act;
+    using Geo = StemMfmaGeom;
+    constexpr int KW = 7, PADS = 3, NCH = 2, S0 = 2;
+    constexpr int NB = C / 16;          // 16-column blocks
+    constexpr int RB = Geo::RB;
+    constexpr int PR = Geo::PR;         // conv rows per pass
+    constexpr int CP = C + 4;           // LDS row pitch (floats)
+    static_assert(C % 16 == 0, "whole column blocks");
+    __shared__ __attribute__((aligned(16))) float cb[(PR + 1) * CP];   // row 0: conv row before the pass
+    extern __shared__ float xs[];       // [NCH][Geo::pitch(window)], samples at Geo::PADL
+    const int b = blockIdx.x;
+    const int64_t wi = a.first_window + b;
+    const int W = a.window;
+    const int XP = Geo::pitch(W);
+    const WinAddr wa = window_addr(a, wi);
+    for (int e = threadIdx.x; e < NCH * (Geo::PADL + Geo::PADR); e += 256) {   // zero pads
+        const int c = e / (Geo::PADL + Geo::PADR), u = e % (Geo::PADL + Geo::PADR);
+        xs[c * XP + (u < Geo::PADL ? u : W + u)] = 0.f;
+    }
+    stage_window(a, wa, xs, XP, Geo::PADL);   // a.n_ch == NCH
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+    const int g = lane >> 4, r16 = lane & 15;
+    // B operand of k-step s for column block nb: k = 4s + g is channel k / 8, tap k % 8
+    float bw[4][NB], bias[NB];
+#pragma unroll
+    for (int nb = 0; nb < NB; ++nb) {
+        bias[nb] = a.b[nb * 16 + r16];
+#pragma unroll
+        for (int st = 0; st < 4; ++st) {
+            const int k = 4 * st + g, ci = k >> 3, j = k & 7;
+            bw[st][nb] = j < KW ? a.w[((nb * 16 + r16) * NCH + ci) * KW + j] : 0.f;
+        }
+    }
+    for (int e = tid; e < CP; e += 256) cb[e] = 0.f;   // conv row -1 never wins (ReLU outputs are >= 0)
+    __syncthreads();
+    Act* out = (Act*)a.out + (size_t)b * a.L_out * C;
+    constexpr int VE = 16 / (int)sizeof(Act);
+    constexpr int VPR = C / VE;
+    constexpr int NV = (PR / 2) * VPR;
+    float vmax = 0.f;
+    const int n_pass = (a.L_conv + PR - 1) / PR;
+    for (int ps = 0; ps < n_pass; ++ps) {
+        // all A operands of the pass first (clamped reads, zero padding by
+        // select), then RB x NB independent accumulation chains
+        // A operands of the pass: k = 4 st + g is channel st / 2, tap 4 (st & 1) + g
+        // (tap 7 meets a zero weight); sample 2q - 3 + tap of the padded row
+        float xa[RB][4];
+        const float* xl = xs + Geo::PADL - PADS + 2 * (ps * PR + wv * RB * 16 + r16) + g;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int st = 0; st < 4; ++st) xa[rb][st] = xl[(st >> 1) * XP + 2 * 16 * rb + 4 * (st & 1)];
+        f4v acc[RB][NB];
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb) acc[rb][nb] = f4v{bias[nb], bias[nb], bias[nb], bias[nb]};
+#pragma unroll
+        for (int st = 0; st < 4; ++st)
+#pragma unroll
+            for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+                for (int nb = 0; nb < NB; ++nb)
+                    acc[rb][nb] = __builtin_amdgcn_mfma_f32_16x16x4f32(xa[rb][st], bw[st][nb], acc[rb][nb], 0, 0, 0);
+        // ReLU; rows past the conv output (a last, partial pass) are zero:
+        // they never win the pool
+        const bool full = (ps + 1) * PR <= a.L_conv;
+#pragma unroll
+        for (int rb = 0; rb < RB; ++rb)
+#pragma unroll
+            for (int nb = 0; nb < NB; ++nb)
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = (wv * RB + rb) * 16 + g * 4 + r;
+                    const float v = fmaxf(acc[rb][nb][r], 0.f);
+                    cb[(1 + row) * CP + nb * 16 + r16] = (full || ps * PR + row < a.L_conv) ? v : 0.f;
+                }
+        __syncthreads();
+        // pooled p = ps PR/2 + pl takes conv rows 2p - 1 .. 2p + 1, i.e. LDS rows 2pl .. 2pl + 2
+        for (int v = tid; v < NV; v += 256) {
+            const int pl = v / VPR, c0 = (v % VPR) * VE;
+            const int p = ps * (PR / 2) + pl;
+            if (p >= a.L_out) continue;
+            float r[VE];
+#pragma unroll
+            for (int e = 0; e < VE; ++e)
+                r[e] = fmaxf(fmaxf(cb[(2 * pl) * CP + c0 + e], cb[(2 * pl + 1) * CP + c0 + e]), cb[(2 * pl + 2) * CP + c0 + e]);
+            Act* o = out + (size_t)p * C + c0;
+            if constexpr (sizeof(Act) == 4) {
+                *(float4*)o = make_float4(r[0], r[1], r[2], r[3]);
+                vmax = fmaxf(vmax, fmaxf(fmaxf(r[0], r[1]), fmaxf(r[2], r[3])));
+            } else {
+                uint32_t u4[4];
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    u4[e] = pack_bf16x2(r[2 * e], r[2 * e + 1]);
+                    if constexpr (P::kFP8)
+                        vmax = fmaxf(vmax, fmaxf(__uint_as_float(u4[e] << 16), __uint_as_float(u4[e] & 0xFFFF0000u)));
+                }
+                *(uint4*)o = make_uint4(u4[0], u4[1], u4[2], u4[3]);
+            }
+        }
+        __syncthreads();
+        for (int e = tid; e < CP; e += 256) cb[e] = cb[PR * CP + e];   // carry the pass's last conv row
+        __syncthreads();
     }
     if constexpr (P::kFP8) {
         for (int off = 32; off > 0; off >>= 1) vmax = fmaxf(vmax, __shfl_xor(vmax, off));

@@ -88,6 +88,13 @@ def test_shifts_and_wrap():
     got = P.Net(TINY_ARCH, params, "f32").score_windows(dev(y), 2048, 5, shifts=shifts, wrap=n).cpu().numpy()
     ref = oracle_logits(params, TINY_ARCH, y, 2048, 5, np.array(shifts), n)
     np.testing.assert_allclose(got, ref, atol=2e-5, rtol=1e-5)
+    # the strided, pooled ResNet stem reads the same circular windows
+    rp = make_params(RESNET_ARCH, seed=29)
+    got = P.Net(RESNET_ARCH, rp, "f32").score_windows(dev(y), 2048, 5, shifts=shifts, wrap=n).cpu().numpy()
+    ref = oracle_logits(rp, RESNET_ARCH, y, 2048, 5, np.array(shifts), n)
+    assert np.abs(got - ref).max() < TOL["f32"]
+    with pytest.raises(P.AframeError, match="EINVAL"):   # a wrap shorter than a window
+        P.Net(TINY_ARCH, params, "f32").score_windows(dev(y), 2048, 1, shifts=shifts, wrap=3000)
 
 
 def test_edge_cases():
