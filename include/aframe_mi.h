@@ -272,6 +272,43 @@ void af_graph_destroy(af_graph* graph);
 af_status af_integrate(const float* p, int64_t n, int64_t width, float* out, af_stream stream);
 
 /* ------------------------------------------------------------------------
+ * Clustering (Sec. II: the integrated series is clustered so that one event
+ * yields one trigger, whose detection statistic is the maximum integrated
+ * value over an 8 s window).  Reading: sample i of a series is a candidate iff
+ *   x[i] >  x[j] for every j in [i - half, i)   and
+ *   x[i] >= x[j] for every j in (i, i + half],
+ * with j limited to i's own series; so equal values resolve to the earliest,
+ * candidates of one series lie more than `half` samples apart, and NaN is
+ * never a candidate and blocks every candidate within half of it.
+ * half = 4 s x the statistic's rate (64 at 16 Hz, 4 at 1 Hz), at most 1024.
+ * x: device [n] FP32, n < 2^31.  Series s is x[off[s] .. off[s+1]) for a
+ * device int64 array off[n_series + 1], non-decreasing, off[0] = 0,
+ * off[n_series] = n; offsets may be NULL when n_series == 1.
+ * Outputs (device): the first min(count, max_out) candidates in ascending
+ * order, their sample indices in idx and values in val, and the total count
+ * in *n_found (device int64).  Asynchronous on `stream`; ws (device) must
+ * hold af_cluster_workspace_bytes(n).  Host-checked errors return AF_EINVAL.
+ * ------------------------------------------------------------------------ */
+size_t af_cluster_workspace_bytes(int64_t n);
+af_status af_cluster(const float* x, int64_t n, const int64_t* offsets, int64_t n_series, int64_t half,
+                     int64_t* idx, float* val, int64_t max_out, int64_t* n_found, void* ws, size_t ws_bytes,
+                     af_stream stream);
+
+/* ------------------------------------------------------------------------
+ * False alarm rate (Sec. IX: the number of background (timeslide) events
+ * with a detection statistic greater than the one of interest, divided by
+ * the background livetime):
+ *   far[q] = #{i < n_bg : bg[i] > x[q]} / livetime        (events per second)
+ * bg: device [n_bg] FP32 background statistics; x: device [n_q] FP32 queries;
+ * far: device [n_q] FP64.  Counts are exact (integers); the division is FP64.
+ * Work is n_q x n_bg comparisons.  livetime > 0 in seconds.  Asynchronous on
+ * `stream`; ws (device) must hold af_far_workspace_bytes(n_q).
+ * ------------------------------------------------------------------------ */
+size_t af_far_workspace_bytes(int64_t n_q);
+af_status af_far(const float* bg, int64_t n_bg, double livetime, const float* x, int64_t n_q, double* far,
+                 void* ws, size_t ws_bytes, af_stream stream);
+
+/* ------------------------------------------------------------------------
  * Streaming server (Sec. VI: clients stream strain to a snapshotter that keeps
  * the recent state, a whitener that estimates the PSD from the first 64 s of
  * that state, and the network; Table III: online latencies).

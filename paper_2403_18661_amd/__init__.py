@@ -35,7 +35,7 @@ def _check_dev(t, name, dtypes):
         raise TypeError(f"{name} must be a CUDA (HIP) tensor")
     if t.dtype not in dtypes:
         raise TypeError(f"{name} must have dtype in {dtypes}, got {t.dtype}")
-    if t.stride(-1) != 1:
+    if t.numel() > 0 and t.stride(-1) != 1:
         raise ValueError(f"{name} must be contiguous in its last dimension")
 
 
@@ -289,4 +289,40 @@ def integrate(p, width, out=None, stream=None):
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=p.device)
     check(lib().af_integrate(_ptr(p), n, width, _ptr(out), _stream(stream)))
+    return out
+
+
+def cluster(x, half, offsets=None, max_out=None, stream=None):
+    """Candidate events of the statistic x [n] (af_cluster): sample i is kept
+    iff it beats every sample up to `half` before it and ties or beats every
+    sample up to `half` after it, within its series (offsets: int64 [n_series
+    + 1] device tensor, or None for one series).  Returns (idx int64, val
+    float32) device tensors, ascending; waits for the count."""
+    _check_dev(x, "x", (torch.float32,))
+    n = x.numel()
+    n_series = 1
+    if offsets is not None:
+        _check_dev(offsets, "offsets", (torch.int64,))
+        n_series = offsets.numel() - 1
+    if max_out is None:
+        max_out = n
+    idx = torch.empty(max(max_out, 1), dtype=torch.int64, device=x.device)
+    val = torch.empty(max(max_out, 1), dtype=torch.float32, device=x.device)
+    found = torch.empty(1, dtype=torch.int64, device=x.device)
+    ws = _workspace(lib().af_cluster_workspace_bytes(n), x.device)
+    check(lib().af_cluster(_ptr(x), n, _ptr(offsets) if offsets is not None else None, n_series, half, _ptr(idx),
+                           _ptr(val), max_out, _ptr(found), _ptr(ws), ws.numel(), _stream(stream)))
+    k = min(int(found.item()), max_out)
+    return idx[:k], val[:k]
+
+
+def far(bg, livetime, x, stream=None):
+    """False alarm rates (af_far): #{background > x[q]} / livetime per query,
+    FP64 [n_q]."""
+    _check_dev(bg, "bg", (torch.float32,))
+    _check_dev(x, "x", (torch.float32,))
+    out = torch.empty(x.numel(), dtype=torch.float64, device=x.device)
+    ws = _workspace(lib().af_far_workspace_bytes(x.numel()), x.device)
+    check(lib().af_far(_ptr(bg) if bg.numel() else None, bg.numel(), float(livetime), _ptr(x), x.numel(), _ptr(out),
+                       _ptr(ws), ws.numel(), _stream(stream)))
     return out

@@ -46,6 +46,10 @@ SIGNATURES = {
     "af_net_n_layers": (c_i64, [c_vp]),
     "af_net_fused": (c_int, [c_vp]),
     "af_net_autotune": (c_int, [c_vp, c_i64, c_vp, c_sz, c_vp, ctypes.POINTER(c_i64)]),
+    "af_cluster_workspace_bytes": (c_sz, [c_i64]),
+    "af_cluster": (c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "af_far_workspace_bytes": (c_sz, [c_i64]),
+    "af_far": (c_int, [c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "af_net_set_layer_tile": (c_int, [c_vp, c_i64, ctypes.c_int32]),
     "af_net_layer_tile": (c_int, [c_vp, c_i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
