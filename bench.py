@@ -152,6 +152,58 @@ def timeslide_leg(args, P, log):
     return res
 
 
+def rate_leg(args, P, log, xd, arch, params):
+    """Inference-rate sweep: the hour's whitened series scored at 1, 2, 4, 8,
+    16 and 64 Hz (the rates the paper compared) and 2048 Hz (its online rate)
+    by the ResNet in the mode that keeps tau >= 0.99; windows/s and seconds of
+    data analysed per second.  Rates above 16 Hz score the first part of the
+    hour only (at most 1.2M windows, to bound the run).  Then one stream served
+    at 2048 Hz (a window every sample, 1 s integration over 2048 windows)."""
+    import torch
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from paper_2403_18661_amd.stream import Server, run_realtime
+    from synth.noise import coloured_noise
+    from synth.workloads import PSD_LEN
+    fs = 2048
+    net = P.Net(arch, params, "bf16f")
+    path = OfflinePath(net, xd.shape[1], PathConfig(psd_len=PSD_LEN), batch=args.batch)
+    path.psd_stage(xd)
+    y = path.whiten_stage(xd).clone()
+    del path
+    net.autotune(batch=min(args.batch, 2048))
+    out = {"precision": "bf16f", "rates": {}}
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ws = None
+    for rate in (1, 2, 4, 8, 16, 64, 2048):
+        stride = fs // rate
+        n_w = min((y.shape[1] - net.window) // stride + 1, 1_200_000)
+        if ws is None:
+            ws = torch.empty(net.workspace_bytes(args.batch), dtype=torch.uint8, device="cuda")
+        logits = torch.empty(n_w, dtype=torch.float32, device="cuda")
+        net.score_windows(y, stride, n_w, batch=args.batch, out=logits, ws=ws)   # warm-up
+        torch.cuda.synchronize()
+        ev0.record()
+        net.score_windows(y, stride, n_w, batch=args.batch, out=logits, ws=ws)
+        ev1.record()
+        ev1.synchronize()
+        ms = ev0.elapsed_time(ev1)
+        wps = n_w / (ms * 1e-3)
+        out["rates"][str(rate)] = {"stride": stride, "windows": n_w, "ms": ms, "windows_per_s": wps,
+                                   "data_s_per_s": wps / rate}
+        log(f"rate {rate} Hz: {n_w} windows in {ms:.1f} ms, {wps:.0f} windows/s, {wps / rate:.0f} s of data per s")
+    del y, ws
+    torch.cuda.empty_cache()
+    srv = Server(P.Net(arch, params, "bf16f"), max_streams=1, hbm_budget=64 << 30, stride=1, integrate_width=fs)
+    n = int((66 + args.stream_seconds + 10) * fs)
+    srv.admit()
+    st = run_realtime(srv, [coloured_noise(n, seed=7000)], args.stream_seconds, fs=fs, seed=7, log=log)
+    srv.close()
+    out["online_2048hz"] = st
+    log(f"online 2048 Hz, 1 stream: p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms, "
+        f"{st['windows_per_s']:.0f} windows/s")
+    return out
+
+
 def stream_leg(args, P, log):
     """Streaming server: S independent two-detector streams, 1 s chunks with
     exponential inter-arrival (mean 1 s), rolling 64 s PSD every 8 s, windows
@@ -193,6 +245,7 @@ def main():
                     help="before anything else, run one plain device copy of this many MiB (a known-size "
                          "reference for hardware byte counters)")
     ap.add_argument("--no-stream", action="store_true")
+    ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -338,6 +391,8 @@ def main():
     }
     if not args.no_timeslide:
         out["timeslide"] = timeslide_leg(args, P, log)
+    if not args.no_rates:
+        out["rates"] = rate_leg(args, P, log, xd, arch, params)
     if not args.no_stream:
         out["stream"] = stream_leg(args, P, log)
         if "64" in out["stream"]:
