@@ -204,6 +204,59 @@ def rate_leg(args, P, log, xd, arch, params):
     return out
 
 
+def inject_leg(args, P, log):
+    """Injection campaign on the device: 8192 polarisation pairs of 2 s
+    projected onto H1 and L1 (antenna patterns and geocentric delays for
+    isotropic sky positions) and rescaled to network SNRs uniform in 4-20
+    against the analytic PSD; the oracle doing the same for a sample of 16."""
+    import torch
+    from synth.detectors import ligo_detectors, polarisation_pairs, sky_draws
+    from synth.noise import analytic_psd
+    import oracle
+    fs, n, n_inj = 2048.0, 4096, 8192
+    hp1, hc1 = polarisation_pairs(256, n, fs, seed=21)
+    reps_tile = n_inj // 256
+    hp = torch.from_numpy(np.tile(hp1, (reps_tile, 1))).cuda()
+    hc = torch.from_numpy(np.tile(hc1, (reps_tile, 1))).cuda()
+    sky_h = sky_draws(n_inj, seed=22)
+    sky = torch.from_numpy(sky_h).cuda()
+    det = ligo_detectors()
+    df = fs / n
+    f = np.arange(n // 2 + 1) * df
+    psd_h = np.repeat((analytic_psd(np.maximum(f, 1.0)) * 1e42)[None, :], 2, axis=0)
+    psd = torch.from_numpy(psd_h).cuda()
+    tgt_h = np.random.default_rng(23).uniform(4.0, 20.0, n_inj)
+    tgt = torch.from_numpy(tgt_h).cuda()
+    out = torch.empty((n_inj, 2, n), dtype=torch.float32, device="cuda")
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+    P.project(hp, hc, sky, det, fs, out=out)
+    P.snr_rescale(out, psd, df, fs, 20.0, target=tgt)
+    reps = 5
+    ev[0].record()
+    for _ in range(reps):
+        P.project(hp, hc, sky, det, fs, out=out)
+    ev[1].record()
+    for _ in range(reps):
+        P.snr_rescale(out, psd, df, fs, 20.0, target=tgt)
+    ev[2].record()
+    ev[2].synchronize()
+    proj_ms = ev[0].elapsed_time(ev[1]) / reps
+    snr_ms = ev[1].elapsed_time(ev[2]) / reps
+    k = 16
+    t0 = time.perf_counter()
+    sig = oracle.project(hp1[:k], hc1[:k], sky_h[:k], det, fs)
+    rho = oracle.network_snr(sig, psd_h, df, fs, 20.0)
+    sig *= (tgt_h[:k] / rho)[:, None, None]
+    cpu_s = time.perf_counter() - t0
+    res = {"injections": n_inj, "samples_each": n, "detectors": 2, "project_ms": proj_ms, "snr_rescale_ms": snr_ms,
+           "injections_per_s": n_inj / ((proj_ms + snr_ms) * 1e-3),
+           "oracle_injections_per_s": k / cpu_s, "oracle_sample": f"{k} injections, one host thread"}
+    res["gpu_over_oracle"] = res["injections_per_s"] / res["oracle_injections_per_s"]
+    log(f"inject: {n_inj} x 2 x {n} projected in {proj_ms:.3f} ms, SNR + rescale in {snr_ms:.3f} ms "
+        f"({res['injections_per_s']:.0f}/s; oracle {res['oracle_injections_per_s']:.1f}/s)")
+    return res
+
+
 def stream_leg(args, P, log):
     """Streaming server: S independent two-detector streams, 1 s chunks with
     exponential inter-arrival (mean 1 s), rolling 64 s PSD every 8 s, windows
@@ -246,6 +299,7 @@ def main():
                          "reference for hardware byte counters)")
     ap.add_argument("--no-stream", action="store_true")
     ap.add_argument("--no-rates", action="store_true")
+    ap.add_argument("--no-inject", action="store_true")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -393,6 +447,8 @@ def main():
         out["timeslide"] = timeslide_leg(args, P, log)
     if not args.no_rates:
         out["rates"] = rate_leg(args, P, log, xd, arch, params)
+    if not args.no_inject:
+        out["inject"] = inject_leg(args, P, log)
     if not args.no_stream:
         out["stream"] = stream_leg(args, P, log)
         if "64" in out["stream"]:

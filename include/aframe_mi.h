@@ -304,6 +304,41 @@ af_status af_cluster(const float* x, int64_t n, const int64_t* offsets, int64_t 
  * Work is n_q x n_bg comparisons.  livetime > 0 in seconds.  Asynchronous on
  * `stream`; ws (device) must hold af_far_workspace_bytes(n_q).
  * ------------------------------------------------------------------------ */
+/* ------------------------------------------------------------------------
+ * Injection on the device (Sec. IV, signal injection: intrinsic polarisation
+ * series are projected onto the interferometers and rescaled to a sampled
+ * SNR, the total SNR of the detector network per the footnote of Sec. I).
+ *
+ * af_project: for injection i and detector d,
+ *   out[i][d][k] = F+ hp_i(t_k - dt) + Fx hc_i(t_k - dt),  t_k = k / fs,
+ * with F+ = D : e+, Fx = D : ex, D = (x x^T - y y^T)/2 from the detector's
+ * arm unit vectors x, y, the polarisation tensors e+ = X X^T - Y Y^T,
+ * ex = X Y^T + Y X^T of the basis X = cos(psi) e_a + sin(psi) e_d,
+ * Y = -sin(psi) e_a + cos(psi) e_d around the source direction
+ * s = (cos dec cos phi, cos dec sin phi, sin dec), phi = ra - gmst, with
+ * e_a = (-sin phi, cos phi, 0), e_d = (-sin dec cos phi, -sin dec sin phi,
+ * cos dec); and dt = -(r . s)/c for the detector vertex r (metres, Earth-
+ * fixed).  hp, hc are linearly interpolated (0 outside [0, len)).  FP64
+ * arithmetic, FP32 output.
+ *   hp, hc: device [n_inj][len] FP32; sky: device [n_inj][4] FP64 (ra, dec,
+ *   psi, gmst; radians); det: HOST [n_det][9] FP64 (vertex, x arm, y arm),
+ *   1 <= n_det <= 4; out: device [n_inj][n_det][len] FP32.
+ *
+ * af_snr_rescale: network optimal SNR of sig[i] = [n_det][len] series,
+ *   snr[i]^2 = sum_d 4 (fs/len) sum_{j : f_j >= f_low, j < len/2} |H_dj|^2 / S_d(f_j),
+ *   H_dj = (1/fs) sum_k sig[i][d][k] exp(-2 pi i j k / len),  f_j = j fs/len,
+ * S_d linearly interpolated on the grid m * df of psd[d] (device [n_det][n_freq]
+ * FP64; bins with S <= 0 or beyond the grid skipped); then, when target
+ * (device [n_inj] FP64) is not NULL and snr > 0, sig[i] *= target[i] / snr[i]
+ * in place.  FP64 FFT; len a power of two in [2, 8192].  snr: device [n_inj].
+ * Both asynchronous on `stream`; AF_EINVAL for host-checked errors.
+ * ------------------------------------------------------------------------ */
+af_status af_project(const float* hp, const float* hc, int64_t n_inj, int64_t len, double fs, const double* det,
+                     int64_t n_det, const double* sky, float* out, af_stream stream);
+af_status af_snr_rescale(float* sig, int64_t n_inj, int64_t n_det, int64_t len, double fs, const double* psd,
+                         int64_t n_freq, double df, double f_low, const double* target, double* snr,
+                         af_stream stream);
+
 size_t af_far_workspace_bytes(int64_t n_q);
 af_status af_far(const float* bg, int64_t n_bg, double livetime, const float* x, int64_t n_q, double* far,
                  void* ws, size_t ws_bytes, af_stream stream);

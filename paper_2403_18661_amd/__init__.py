@@ -316,6 +316,38 @@ def cluster(x, half, offsets=None, max_out=None, stream=None):
     return idx[:k], val[:k]
 
 
+def project(hp, hc, sky, det, fs=2048.0, out=None, stream=None):
+    """Polarisations hp, hc [n_inj, len] float32 projected onto detectors
+    (af_project); sky [n_inj, 4] float64 device (ra, dec, psi, gmst); det:
+    host array [n_det, 9] (vertex m, x arm, y arm).  -> [n_inj, n_det, len]."""
+    _check_dev(hp, "hp", (torch.float32,))
+    _check_dev(hc, "hc", (torch.float32,))
+    _check_dev(sky, "sky", (torch.float64,))
+    det = np.ascontiguousarray(det, dtype=np.float64).reshape(-1, 9)
+    n_inj, n = hp.shape
+    if out is None:
+        out = torch.empty((n_inj, det.shape[0], n), dtype=torch.float32, device=hp.device)
+    check(lib().af_project(_ptr(hp), _ptr(hc), n_inj, n, float(fs), det.ctypes.data_as(ctypes.c_void_p),
+                           det.shape[0], _ptr(sky), _ptr(out), _stream(stream)))
+    return out
+
+
+def snr_rescale(sig, psd, df, fs=2048.0, f_low=20.0, target=None, stream=None):
+    """Network optimal SNR of sig [n_inj, n_det, len] against psd [n_det,
+    n_freq] float64 on the grid m*df (af_snr_rescale); with target
+    [n_inj] float64, sig is scaled in place to it.  Returns snr float64."""
+    _check_dev(sig, "sig", (torch.float32,))
+    _check_dev(psd, "psd", (torch.float64,))
+    n_inj, n_det, n = sig.shape
+    snr = torch.empty(n_inj, dtype=torch.float64, device=sig.device)
+    if target is not None:
+        _check_dev(target, "target", (torch.float64,))
+    check(lib().af_snr_rescale(_ptr(sig), n_inj, n_det, n, float(fs), _ptr(psd), psd.shape[-1], float(df),
+                               float(f_low), _ptr(target) if target is not None else None, _ptr(snr),
+                               _stream(stream)))
+    return snr
+
+
 def far(bg, livetime, x, stream=None):
     """False alarm rates (af_far): #{background > x[q]} / livetime per query,
     FP64 [n_q]."""

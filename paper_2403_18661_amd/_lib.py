@@ -50,6 +50,8 @@ SIGNATURES = {
     "af_cluster": (c_int, [c_vp, c_i64, c_vp, c_i64, c_i64, c_vp, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
     "af_far_workspace_bytes": (c_sz, [c_i64]),
     "af_far": (c_int, [c_vp, c_i64, c_dbl, c_vp, c_i64, c_vp, c_vp, c_sz, c_vp]),
+    "af_project": (c_int, [c_vp, c_vp, c_i64, c_i64, c_dbl, c_vp, c_i64, c_vp, c_vp, c_vp]),
+    "af_snr_rescale": (c_int, [c_vp, c_i64, c_i64, c_i64, c_dbl, c_vp, c_i64, c_dbl, c_dbl, c_vp, c_vp, c_vp]),
     "af_net_set_layer_tile": (c_int, [c_vp, c_i64, ctypes.c_int32]),
     "af_net_layer_tile": (c_int, [c_vp, c_i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
