@@ -63,10 +63,12 @@ template <int KW, int S>
 Cands cands_f32(int c_out) {
     if (c_out % 128 == 0)
         return {make_cfg<PF32, KW, S, 2, 2, 3, 4, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, false>(),
-                make_cfg<PF32, KW, S, 2, 2, 2, 4, 16, 1, false>()};
+                make_cfg<PF32, KW, S, 2, 2, 2, 4, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
+                make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 0>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
     if (c_out == 64)
         return {make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 1, false>(),
-                make_cfg<PF32, KW, S, 2, 2, 2, 2, 16, 1, false>()};
+                make_cfg<PF32, KW, S, 2, 2, 2, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
+                make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
     if constexpr (KW == 7 && S == 1) {
         if (c_out == 32)
             return {make_cfg<PF32, 7, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 2, 16, 1, false>(),
