@@ -1095,8 +1095,21 @@ __global__ void __launch_bounds__(256) gap_fc_kernel(const void* act, int L, int
     // thread -> channel c = tid % C, time stride 256 / C (C divides 256)
     const int per = 256 / C;
     const int c = threadIdx.x % C, t0 = threadIdx.x / C;
+    // sixteen loads in flight per step (a clamped index past the end reads a
+    // valid element that then adds an exact zero), summed in time order
+    constexpr int U = 16;
     float s = 0.f;
-    for (int t = t0; t < L; t += per) s += act_to_f32<P>(x[(size_t)t * C + c]);
+    for (int t = t0; t < L; t += per * U) {
+        float v[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int tu = t + u * per;
+            const float e = act_to_f32<P>(x[(size_t)(tu < L ? tu : L - 1) * C + c]);
+            v[u] = tu < L ? e : 0.f;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) s += v[u];
+    }
     part[threadIdx.x] = s;
     __syncthreads();
     if (threadIdx.x < C) {
