@@ -110,7 +110,7 @@ def run_realtime(server, data, seconds, fs=2048, chunk_s=1.0, prefill_s=66.0, se
     (pushed and ticked at once) so that its PSD background and first windows
     exist; latency statistics are reset after the pre-fill.  Then for
     `seconds` of wall time each stream's next chunk arrives after an
-    exponential gap of mean chunk_s; the driver pushes chunks as their arrival
+    exponential gap of mean chunk_s; the loop pushes chunks as their arrival
     times pass and runs a tick whenever anything is pending.
     """
     rng = np.random.default_rng(seed)
