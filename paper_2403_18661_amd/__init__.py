@@ -122,12 +122,15 @@ def whiten_apply(x, resp, n_psd, fs, prescale=1.0, psd_hop=0, fduration=1.0, out
 def pack_params(params, arch):
     """Flatten a name -> array parameter dict into the C ABI's order: per conv
     (stem; per block conv1, conv2, [proj]) weight then BN gamma, beta, mean,
-    var; then FC weight and bias.  `arch` provides block_list()."""
+    var (GroupNorm nets: gamma, beta); then FC weight and bias.  `arch`
+    provides block_list() and norm."""
     parts = []
+
+    keys = ("gamma", "beta") if getattr(arch, "norm", "bn") == "gn" else ("gamma", "beta", "mean", "var")
 
     def conv(c, bn):
         parts.append(np.asarray(params[c + ".w"], np.float64).ravel())
-        for k in ("gamma", "beta", "mean", "var"):
+        for k in keys:
             parts.append(np.asarray(params[f"{bn}.{k}"], np.float64).ravel())
 
     conv("stem.conv", "stem.bn")

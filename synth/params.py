@@ -1,14 +1,18 @@
 """Architectures and seeded random parameters of the 1D residual scoring network.
 
 The paper's network is a ResNet34 variant with 1D convolutions (Sec. II); the
-workloads here use a folded-BatchNorm variant with kernel 7.  Trained weights are
-not available, so parameters are drawn from a seed:
+main workloads use a folded-BatchNorm variant with kernel 7, and the paper's own
+form (GroupNorm in place of BatchNorm, Sec. II; kernel length 3, Sec. IX) is
+`norm="gn"`.  Trained weights are not available, so parameters are drawn from
+a seed:
 
 * conv weights: He-normal, std sqrt(2 / (C_in k)); convs carry no bias;
 * BatchNorm (eps 1e-5): gamma ~ U(0.9, 1.1) except the last BN of each residual
   branch, gamma ~ U(0.2, 0.3) (a damped residual branch keeps activations O(1)
   through 16 blocks without running the network to calibrate statistics);
   beta ~ N(0, 0.02^2), running mean ~ N(0, 0.05^2), running var ~ U(0.8, 1.25);
+* GroupNorm (eps 1e-5): per-channel gamma and beta drawn like BatchNorm's
+  (the damped range for the last norm of each residual branch);
 * FC: He-normal weight (fan-in C), bias 0.
 
 Parameters are returned as an ordered dict name -> float64 array; the order is
@@ -31,6 +35,8 @@ class NetArch:
     widths: tuple
     blocks: tuple
     window: int = 3072
+    norm: str = "bn"         # "bn" (folded BatchNorm) or "gn" (GroupNorm)
+    groups: int = 0          # GroupNorm groups per layer
 
     def block_list(self):
         """Yield (prefix, c_in, c_out, stride, has_proj) for every BasicBlock."""
@@ -47,6 +53,11 @@ TINY_ARCH = NetArch("tiny", in_ch=2, stem_ch=16, kernel=7, stem_stride=1,
                     stem_pool=False, widths=(16,), blocks=(2,))
 RESNET_ARCH = NetArch("resnet", in_ch=2, stem_ch=32, kernel=7, stem_stride=2,
                       stem_pool=True, widths=(32, 64, 128, 256), blocks=(3, 4, 6, 3))
+# the paper's form: GroupNorm, kernel length 3, ResNet34 depth
+GN_ARCH = NetArch("resnet34-gn", in_ch=2, stem_ch=32, kernel=3, stem_stride=2, stem_pool=True,
+                  widths=(32, 64, 128, 256), blocks=(3, 4, 6, 3), norm="gn", groups=8)
+TINY_GN_ARCH = NetArch("tiny-gn", in_ch=2, stem_ch=32, kernel=3, stem_stride=2, stem_pool=True,
+                       widths=(32, 64), blocks=(2, 1), window=512, norm="gn", groups=8)
 
 
 def _bn(rng, c, damped=False):
@@ -69,6 +80,8 @@ def make_params(arch, seed=0):
 
     def bn(name, c, damped=False):
         for key, v in _bn(rng, c, damped).items():
+            if arch.norm == "gn" and key in ("mean", "var"):
+                continue                      # GroupNorm has no running statistics
             p[f"{name}.{key}"] = v
 
     conv("stem.conv", arch.stem_ch, arch.in_ch, k)
