@@ -159,6 +159,22 @@ typedef struct af_net af_net;
  * Synchronous.  *out receives the handle. */
 af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n_params,
                         af_precision precision, af_net** out);
+/* The paper's own form of the network (Sec. II: GroupNorm in place of
+ * BatchNorm; Sec. IX: convolutions of kernel length 3 with global pooling):
+ * every conv has no bias and is followed by GroupNorm with `groups` groups of
+ * consecutive channels (per window: mean and biased variance over the group's
+ * channels and all samples, eps 1e-5, then per-channel gamma, beta), in the
+ * same places as the BatchNorms of af_net_create's network (stem, each conv of
+ * a block, each projection).  params (host, float64): per conv, weight
+ * [C_out][C_in][k] then gamma [C_out], beta [C_out]; then fc weight [C_last]
+ * and fc bias [1].  desc->kernel must be 3; stem_ch and every width a power of
+ * two in [16, 256] divisible by groups; precision AF_F32, or AF_BF16_F32ACT
+ * (BF16 conv operands, FP32 activations and GroupNorm); in_ch must be 2.
+ * The handle works with af_score_windows, the timeslide entry points, the
+ * autotuner and the profile; statistics are taken per window, so a window's
+ * logit does not depend on its batch.  AF_EINVAL on a bad shape or length. */
+af_status af_net_create_gn(const af_net_desc* desc, int32_t groups, const double* params, int64_t n_params,
+                           af_precision precision, af_net** out);
 void af_net_destroy(af_net* net);
 /* Total conv + FC multiply-accumulates per window. */
 int64_t af_net_macs(const af_net* net);
@@ -171,7 +187,9 @@ int64_t af_net_macs(const af_net* net);
 int af_net_fused(const af_net* net);
 af_status af_net_set_fused(af_net* net, int enable);
 
-/* Number of timed layers: stem, each conv in execution order, GAP+FC head. */
+/* Number of timed layers: stem, each conv in execution order, GAP+FC head;
+ * GroupNorm nets (af_net_create_gn) have one more, after the head, that
+ * collects every GroupNorm launch (the stem's included). */
 int64_t af_net_n_layers(const af_net* net);
 /* Kernel timing (a tracing aid, Sec. VIII reports per-stage latencies).
  * Between begin and end, every af_score_windows call on this net records a HIP

@@ -145,7 +145,8 @@ def pack_params(params, arch):
 
 
 class Net:
-    """A scoring network resident on the current device (af_net_create)."""
+    """A scoring network resident on the current device (af_net_create; for an
+    architecture with norm "gn", af_net_create_gn)."""
 
     def __init__(self, arch, params, precision="f32"):
         d = NetDesc()
@@ -159,9 +160,14 @@ class Net:
         self.window = arch.window
         self.in_ch = arch.in_ch
         self.precision = precision
+        self.norm = getattr(arch, "norm", "bn")
         h = ctypes.c_void_p()
-        check(lib().af_net_create(ctypes.byref(d), flat.ctypes.data_as(ctypes.c_void_p), flat.size,
-                                  PRECISIONS[precision], ctypes.byref(h)))
+        if getattr(arch, "norm", "bn") == "gn":
+            check(lib().af_net_create_gn(ctypes.byref(d), arch.groups, flat.ctypes.data_as(ctypes.c_void_p),
+                                         flat.size, PRECISIONS[precision], ctypes.byref(h)))
+        else:
+            check(lib().af_net_create(ctypes.byref(d), flat.ctypes.data_as(ctypes.c_void_p), flat.size,
+                                      PRECISIONS[precision], ctypes.byref(h)))
         self._h = h
 
     def close(self):
@@ -194,13 +200,19 @@ class Net:
     def n_layers(self):
         return lib().af_net_n_layers(self._h)
 
+    @property
+    def n_convs(self):
+        """MFMA conv layers (profile layers 1 .. n_convs)."""
+        return self.n_layers - (3 if self.norm == "gn" else 2)
+
     def profile_begin(self):
         """Start per-kernel HIP-event timing of score_windows calls."""
         check(lib().af_net_profile_begin(self._h))
 
     def profile_end(self):
         """Stop timing; return per-layer dict arrays ms, launches, flops
-        (layer 0 = stem, then convs in execution order, last = head)."""
+        (layer 0 = stem, then convs in execution order, then the head; GroupNorm
+        nets end with one more entry, every GroupNorm launch)."""
         n = self.n_layers
         ms = np.zeros(n)
         la = np.zeros(n, dtype=np.int64)
@@ -221,7 +233,7 @@ class Net:
     def tiles(self):
         """[(rows, out_channels, n_candidates, chosen)] per conv layer."""
         out = []
-        for layer in range(1, self.n_layers - 1):
+        for layer in range(1, self.n_convs + 1):
             v = [ctypes.c_int32() for _ in range(4)]
             check(lib().af_net_layer_tile(self._h, layer, *[ctypes.byref(x) for x in v]))
             out.append(tuple(x.value for x in v))

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "fused_tiny.h"
+#include "gn_kernels.h"
 #include "internal.h"
 
 using namespace afm;
@@ -69,10 +70,10 @@ Cands cands_f32(int c_out) {
         return {make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 1, false>(),
                 make_cfg<PF32, KW, S, 2, 2, 2, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
                 make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
-    if constexpr (KW == 7 && S == 1) {
+    if constexpr ((KW == 7 || KW == 3) && S == 1) {
         if (c_out == 32)
-            return {make_cfg<PF32, 7, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 2, 16, 1, false>(),
-                    make_cfg<PF32, 7, 1, 2, 2, 6, 1, 16, 1, false>()};
+            return {make_cfg<PF32, KW, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, 1, 4, 1, 2, 2, 16, 1, false>(),
+                    make_cfg<PF32, KW, 1, 2, 2, 6, 1, 16, 1, false>()};
         if (c_out == 16)
             return {make_cfg<PF32, 7, 1, 4, 1, 4, 1, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 1, 16, 1, false>()};
     }
@@ -114,6 +115,17 @@ Cands cands_lowp(int c_out) {
     }
 }
 
+// k3 convs of the GroupNorm net (BF16 operands, FP32 activations): the
+// 64-row-multiple tiles as for k7, and for 32 output channels 256 x 32 tiles
+// without the tap-shift reuse.
+template <typename P, int S>
+Cands cands_k3(int c_out) {
+    if (c_out % 64 == 0) return cands_lowp<P, 3, S, 32>(c_out);
+    if (S == 1 && c_out == 32)
+        return {make_cfg<P, 3, 1, 4, 1, 4, 2, 32, 1, false, false>(), make_cfg<P, 3, 1, 4, 1, 2, 2, 32, 1, false, false>()};
+    return {};
+}
+
 template <typename P, int KC>
 Cands cands_shape_lowp(int kw, int s, int c_out) {
     if (kw == 7 && s == 1) return cands_lowp<P, 7, 1, KC>(c_out);
@@ -130,6 +142,8 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int ro
         if (kw == 7 && s == 1) return cands_f32<7, 1>(c_out);
         if (kw == 7 && s == 2) return c_out >= 64 ? cands_f32<7, 2>(c_out) : Cands{};
         if (kw == 1 && s == 2) return c_out >= 64 ? cands_f32<1, 2>(c_out) : Cands{};
+        if (kw == 3 && s == 1) return cands_f32<3, 1>(c_out);
+        if (kw == 3 && s == 2) return c_out >= 64 ? cands_f32<3, 2>(c_out) : Cands{};
         return {};
     }
     const bool kc32 = c_in % 32 == 0;
@@ -151,6 +165,7 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int ro
         }
         if (role == 2 && kw == 7 && s == 1)
             return kc32 ? cands_lowp<PBF16BF, 7, 1, 32>(c_out) : cands_lowp<PBF16BF, 7, 1, 16>(c_out);
+        if (kw == 3) return !kc32 ? Cands{} : s == 1 ? cands_k3<PBF16F, 1>(c_out) : cands_k3<PBF16F, 2>(c_out);
         if (kc32) return cands_shape_lowp<PBF16F, 32>(kw, s, c_out);
         return kw == 7 && s == 1 ? cands_lowp<PBF16F, 7, 1, 16>(c_out) : Cands{};
     }
@@ -219,6 +234,10 @@ struct ConvOp {
     ConvCfg cfg;
     int wpt, tt, tiles_per_win;
     void* d_img = nullptr;         // weight image for cfg (device)
+    // GroupNorm nets: the conv's output buffer is normalised into gn_out (with
+    // gamma, beta at gn_off of the net's table), plus gn_res, then ReLU
+    size_t gn_off = 0;
+    int gn_out = -1, gn_res = -1, gn_relu = 0;
 };
 
 // M tiling of a layer for its tile height: several short windows per tile, or
@@ -281,6 +300,8 @@ struct af_net {
     float* d_ws = nullptr;     // FP8 per-output-channel scales
     float* d_stem = nullptr;   // stem weights [C][in][k] then bias [C]
     float* d_fc = nullptr;     // fc weights [C_last]
+    int gn_groups = 0;         // > 0: GroupNorm net (stem's gamma, beta first in d_gn)
+    float* d_gn = nullptr;     // GroupNorm gamma [C], beta [C] per norm layer
     // kernel timing (af_net_profile_begin/end): one event pair per launch
     bool profiling = false;
     struct Rec {
@@ -319,20 +340,32 @@ void free_net(af_net* n) {
     if (n->d_ws) (void)hipFree(n->d_ws);
     if (n->d_stem) (void)hipFree(n->d_stem);
     if (n->d_fc) (void)hipFree(n->d_fc);
+    if (n->d_gn) (void)hipFree(n->d_gn);
     if (n->d_wfused) (void)hipFree(n->d_wfused);
     if (n->d_bfused) (void)hipFree(n->d_bfused);
     delete n;
 }
 }  // namespace
 
-extern "C" af_status af_net_create(const af_net_desc* d, const double* params, int64_t n_params,
-                                   af_precision prec, af_net** out) {
-    clear_error();
+namespace {
+// groups == 0: BatchNorm net (folded); groups > 0: GroupNorm net
+af_status create_net(const af_net_desc* d, int groups, const double* params, int64_t n_params,
+                     af_precision prec, af_net** out) {
     AF_CHECK_ARG(d && params && out, "desc, params and out must be non-null");
     AF_CHECK_ARG(prec == AF_F32 || prec == AF_BF16 || prec == AF_FP8 || prec == AF_BF16_F32ACT,
                  "unknown precision %d", (int)prec);
     AF_CHECK_ARG(d->in_ch >= 1 && d->in_ch <= 4, "in_ch must be in [1, 4]");
-    AF_CHECK_ARG(d->kernel == 7, "only kernel 7 is implemented");
+    if (groups) {
+        AF_CHECK_ARG(d->kernel == 3 && d->in_ch == 2, "GroupNorm nets are implemented for kernel 3 and 2 inputs");
+        AF_CHECK_ARG(prec == AF_F32 || prec == AF_BF16_F32ACT,
+                     "GroupNorm nets run in AF_F32 or AF_BF16_F32ACT");
+        AF_CHECK_ARG(groups <= 256 && d->stem_ch % groups == 0, "groups must divide stem_ch");
+        for (int st = 0; st < d->n_stages && st < 8; ++st)
+            AF_CHECK_ARG(d->widths[st] % groups == 0 && d->widths[st] >= 16 && 256 % d->widths[st] == 0,
+                         "GroupNorm widths must be powers of two in [16, 256] divisible by groups");
+    } else {
+        AF_CHECK_ARG(d->kernel == 7, "only kernel 7 is implemented");
+    }
     AF_CHECK_ARG(d->stem_stride == 1 || d->stem_stride == 2, "stem_stride must be 1 or 2");
     AF_CHECK_ARG(d->n_stages >= 1 && d->n_stages <= 8, "n_stages must be in [1, 8]");
     AF_CHECK_ARG(d->window >= 16 && d->window <= 16384, "window must be in [16, 16384]");
@@ -342,6 +375,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     if (!net) { set_error("out of host memory"); return AF_ENOMEM; }
     net->desc = *d;
     net->prec = prec;
+    net->gn_groups = groups;
     (void)hipGetDevice(&net->device);
 
     // ---- walk the architecture, fold BN, build the op list --------------------
@@ -350,8 +384,23 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     std::vector<float> stem;       // weights then bias
     std::vector<double> wfold;     // all MFMA conv weights, [C_out][KW][C_in], folded
     std::vector<float> bias;
+    std::vector<float> gnp;        // GroupNorm nets: gamma, beta per norm layer
+    size_t gn_off = 0;             // offset of the last conv's pair in gnp
     auto take_conv = [&](int c_out, int c_in, int kw, std::vector<double>& w, std::vector<double>& b) -> bool {
         const size_t nw = (size_t)c_out * c_in * kw;
+        if (groups) {
+            // weights as they are (no fold, no bias), then gamma and beta
+            if (p + nw + 2 * (size_t)c_out > p_end) return false;
+            w.assign(nw, 0.0);
+            b.assign(c_out, 0.0);
+            for (int o = 0; o < c_out; ++o)
+                for (int c = 0; c < c_in; ++c)
+                    for (int j = 0; j < kw; ++j) w[((size_t)o * kw + j) * c_in + c] = p[((size_t)o * c_in + c) * kw + j];
+            gn_off = gnp.size();
+            for (size_t i = 0; i < 2 * (size_t)c_out; ++i) gnp.push_back((float)p[nw + i]);
+            p += nw + 2 * (size_t)c_out;
+            return true;
+        }
         if (p + nw + 4 * (size_t)c_out > p_end) return false;
         const double* W = p;
         const double *g = W + nw, *be = g + c_out, *mu = be + c_out, *var = mu + c_out;
@@ -379,7 +428,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     net->stem_lout = d->stem_pool ? (net->stem_lconv + 2 - 3) / 2 + 1 : net->stem_lconv;
     net->macs = (int64_t)net->stem_lconv * d->stem_ch * d->in_ch * K;
     net->layer_macs.push_back(net->macs);
-    net->act_elems = (int64_t)net->stem_lout * d->stem_ch;
+    net->act_elems = (int64_t)(groups ? net->stem_lconv : net->stem_lout) * d->stem_ch;   // GN: raw stem output
 
     int L = net->stem_lout, C = d->stem_ch, slot_x = 0, n_slots = 1;
     auto add_conv = [&](int c_in, int c_out, int kw, int s, int l_in, int relu, int in_buf, int out_buf,
@@ -392,7 +441,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         op.amax_out = n_slots++;
         op.w_off = wfold.size();
         op.b_off = bias.size();
-        op.cands = conv_candidates(prec, kw, s, c_in, c_out, out_buf == BR ? 1 : (in_buf == BR ? 2 : 0));
+        op.cands = conv_candidates(prec, kw, s, c_in, c_out, groups ? 0 : out_buf == BR ? 1 : (in_buf == BR ? 2 : 0));
         op.cand = 0;
         op.cfg = op.cands.empty() ? ConvCfg{} : op.cands[0];
         if (!op.cfg.fn) {
@@ -400,6 +449,11 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
             return false;
         }
         if (!take_conv(c_out, c_in, kw, w, b)) { set_error("params too short"); return false; }
+        if (groups) {   // raw conv; GroupNorm, residual and ReLU follow in gn_kernel
+            op.relu = 0;
+            op.res_buf = -1;
+            op.gn_off = gn_off;
+        }
         set_tiling(op);
         wfold.insert(wfold.end(), w.begin(), w.end());
         for (int o = 0; o < c_out; ++o) bias.push_back((float)b[o]);
@@ -428,6 +482,22 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
             } else {
                 slot_x = net->ops.back().amax_out;
             }
+            if (groups) {
+                // buffers: conv1 X -> R, GN(R) -> R, ReLU; with a projection,
+                // proj X -> P, GN(P) -> P, then conv2 R -> X, GN(X) + P -> X,
+                // ReLU; without, conv2 R -> P, GN(P) + X -> X, ReLU
+                const size_t n_ops = net->ops.size();
+                ConvOp& c1 = net->ops[n_ops - (proj ? 3 : 2)];
+                ConvOp& c2 = net->ops[n_ops - 1];
+                c1.gn_out = BR; c1.gn_relu = 1;
+                if (proj) {
+                    ConvOp& pj = net->ops[n_ops - 2];
+                    pj.gn_out = BP; pj.gn_relu = 0;
+                    c2.out_buf = BX; c2.gn_out = BX; c2.gn_res = BP; c2.gn_relu = 1;
+                } else {
+                    c2.out_buf = BP; c2.gn_out = BX; c2.gn_res = BX; c2.gn_relu = 1;
+                }
+            }
             C = wdt;
             L = l_out;
         }
@@ -443,6 +513,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     net->fc_b = (float)p[C];
     net->macs += C;
     net->layer_macs.push_back(C);
+    if (groups) net->layer_macs.push_back(0);   // every GroupNorm launch, timed as one more layer
     net->last_L = L;
     net->last_C = C;
     net->n_slots = n_slots;
@@ -478,6 +549,11 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     }
     net->wfold = wfold;
     net->wscale = wscale_full;
+    if (groups && !upload((void**)&net->d_gn, gnp.data(), gnp.size() * 4)) {
+        free_net(net);
+        set_error("device allocation/upload of the weights failed");
+        return AF_ENOMEM;
+    }
     if (!upload((void**)&net->d_b, bias.data(), bias.size() * 4) ||
         !upload((void**)&net->d_stem, stem.data(), stem.size() * 4) ||
         !upload((void**)&net->d_fc, fc.data(), fc.size() * 4) ||
@@ -488,7 +564,7 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
     }
     // fused whole-network path: stem 2->16 k7 s1, one stage of two 16-channel
     // blocks, BF16
-    const bool tiny = d->in_ch == 2 && d->stem_ch == 16 && d->stem_stride == 1 && !d->stem_pool &&
+    const bool tiny = !groups && d->in_ch == 2 && d->stem_ch == 16 && d->stem_stride == 1 && !d->stem_pool &&
                       d->n_stages == 1 && d->widths[0] == 16 && d->blocks[0] == 2 && net->ops.size() == 4;
     if (tiny && prec == AF_BF16) {
         std::vector<uint16_t> wf(4 * 16 * 128, 0);
@@ -515,6 +591,20 @@ extern "C" af_status af_net_create(const af_net_desc* d, const double* params, i
         net->n_cu = 256;
     *out = net;
     return AF_OK;
+}
+}  // namespace
+
+extern "C" af_status af_net_create(const af_net_desc* d, const double* params, int64_t n_params,
+                                   af_precision prec, af_net** out) {
+    clear_error();
+    return create_net(d, 0, params, n_params, prec, out);
+}
+
+extern "C" af_status af_net_create_gn(const af_net_desc* d, int32_t groups, const double* params,
+                                      int64_t n_params, af_precision prec, af_net** out) {
+    clear_error();
+    AF_CHECK_ARG(groups >= 1, "groups must be >= 1");
+    return create_net(d, groups, params, n_params, prec, out);
 }
 
 extern "C" int af_net_fused(const af_net* net) { return net && net->fused_ok && net->fused_on ? 1 : 0; }
@@ -570,6 +660,20 @@ namespace {
 af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
                         int64_t n_windows, const int64_t* shift, int64_t wrap, const int64_t* table, int n_entries,
                         float* logits, void* ws, size_t ws_bytes, hipStream_t s);
+
+// GroupNorm of nb windows of [L][C] FP32 activations (one workgroup each);
+// gamma and beta at gn_off of the net's table.
+void launch_gn(const af_net* net, const void* in, const void* res, void* out, size_t gn_off, int L, int C, int relu,
+               int pool, int nb, hipStream_t s) {
+    GnArgs g{};
+    g.in = (const float*)in;
+    g.res = (const float*)res;
+    g.out = (float*)out;
+    g.gamma = net->d_gn + gn_off;
+    g.beta = g.gamma + C;
+    g.L = L; g.C = C; g.G = net->gn_groups; g.relu = relu; g.pool = pool;
+    hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
+}
 }
 
 extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
@@ -678,15 +782,33 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         sa.C = d.stem_ch; sa.KW = d.kernel; sa.s0 = d.stem_stride; sa.pool = d.stem_pool;
         sa.L_conv = net->stem_lconv; sa.L_out = net->stem_lout;
         const size_t stem_lds = (size_t)n_ch * window * sizeof(float);
+        const int gn_layer = (int)net->layer_macs.size() - 1;
+        auto gn = [&](const void* in, const void* res, void* out, size_t off, int L, int C, int relu, int pool) {
+            if (!t_begin(gn_layer, nb)) return false;
+            launch_gn(net, in, res, out, off, L, C, relu, pool, nb, s);
+            return hipPeekAtLastError() == hipSuccess && t_end();
+        };
         if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
-        if (!launch_stem(net->prec, d, sa, nb, stem_lds, s)) {
+        if (net->gn_groups) {
+            // raw stem conv into R, then GroupNorm, ReLU (and pool) into X
+            sa.out = buf[BR];
+            hipLaunchKernelGGL((gn_stem_kernel<2, 3>), dim3(nb), dim3(256), stem_lds, s, sa);
+            AF_LAUNCHED();
+            t_end();
+            if (!gn(buf[BR], nullptr, buf[BX], 0, net->stem_lconv, d.stem_ch, 1, d.stem_pool)) {
+                set_error("GroupNorm launch failed: %s", hipGetErrorString(hipGetLastError()));
+                return AF_EHIP;
+            }
+        } else if (!launch_stem(net->prec, d, sa, nb, stem_lds, s)) {
             if (net->prec == AF_F32 || net->prec == AF_BF16_F32ACT)
                 hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
             else if (net->prec == AF_BF16) hipLaunchKernelGGL(stem_kernel<PBF16>, dim3(nb), dim3(256), stem_lds, s, sa);
             else hipLaunchKernelGGL(stem_kernel<PFP8>, dim3(nb), dim3(256), stem_lds, s, sa);
         }
-        AF_LAUNCHED();
-        t_end();
+        if (!net->gn_groups) {
+            AF_LAUNCHED();
+            t_end();
+        }
         int layer = 0;
         for (const ConvOp& op : net->ops) {
             ++layer;
@@ -709,6 +831,11 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             op.cfg.fn(a, s);
             AF_LAUNCHED();
             t_end();
+            if (net->gn_groups && !gn(buf[op.out_buf], op.gn_res >= 0 ? buf[op.gn_res] : nullptr, buf[op.gn_out],
+                                      op.gn_off, op.l_out, op.c_out, op.gn_relu, 0)) {
+                set_error("GroupNorm launch failed: %s", hipGetErrorString(hipGetLastError()));
+                return AF_EHIP;
+            }
         }
         if (!t_begin(layer + 1, nb)) { set_error("profiling event failed"); return AF_EHIP; }
         if (act_size(net->prec) == 4)

@@ -24,7 +24,7 @@ import hashlib
 import os
 import re
 
-KERNEL_SOURCES = ("csrc/net_kernels.h", "csrc/net.hip", "csrc/fused_tiny.h", "csrc/whiten.hip", "csrc/psd.hip",
+KERNEL_SOURCES = ("csrc/net_kernels.h", "csrc/gn_kernels.h", "csrc/net.hip", "csrc/fused_tiny.h", "csrc/whiten.hip", "csrc/psd.hip",
                   "csrc/fft_lds.h")
 
 
