@@ -157,4 +157,120 @@ __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
     }
 }
 
+// GroupNorm of one window per workgroup with the window held in registers
+// (no pool): NT threads, up to R float4s each, so a window of up to 4 NT R
+// elements is read from HBM once instead of twice.  Each thread's channels
+// are fixed (C divides 4 NT); its sums and sums of squares per channel (FP32,
+// R terms each) are reduced in FP64 across the lanes that share channels (lane xor C/4 .. 32), then
+// across the NT / 64 waves and per group in a fixed order.  Then as gn_kernel:
+// scale, shift, residual, ReLU; every element is read and written by one
+// thread, so out may alias in or res.
+template <int NT, int R>
+__global__ void __launch_bounds__(NT) gn_reg_kernel(GnArgs a) {
+    constexpr int NW = NT / 64;
+    __shared__ double part[2][NW][256];
+    __shared__ double chs[2][256];
+    __shared__ float sc[256], sh[256];
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, C = a.C, L = a.L;
+    const size_t b = blockIdx.x;
+    const float4* in = (const float4*)(a.in + b * L * C);
+    const int n4 = L * C / 4;
+    float4 v[R];
+#pragma unroll
+    for (int u = 0; u < R; ++u) v[u] = in[min(tid + NT * u, n4 - 1)];
+    // a thread's R values per channel summed in FP32, the rest of the
+    // reduction in FP64
+    float sf[4] = {0.f, 0.f, 0.f, 0.f}, qf[4] = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        if (tid + NT * u < n4) {
+            const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                sf[k] += e[k];
+                qf[k] = fmaf(e[k], e[k], qf[k]);
+            }
+        }
+    }
+    double s[4], q[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        s[k] = sf[k];
+        q[k] = qf[k];
+    }
+    // lane l holds channels 4l % C .. +3; lanes l and l xor m (m >= C/4) share them
+    for (int off = C / 4; off < 64; off <<= 1)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            s[k] += __shfl_xor(s[k], off);
+            q[k] += __shfl_xor(q[k], off);
+        }
+    if (lane < C / 4)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            part[0][wv][4 * lane + k] = s[k];
+            part[1][wv][4 * lane + k] = q[k];
+        }
+    __syncthreads();
+    if (tid < C) {
+        double cs = 0.0, cq = 0.0;
+        for (int w = 0; w < NW; ++w) {
+            cs += part[0][w][tid];
+            cq += part[1][w][tid];
+        }
+        chs[0][tid] = cs;
+        chs[1][tid] = cq;
+    }
+    __syncthreads();
+    if (tid < C) {
+        const int cpg = C / a.G, g = tid / cpg;
+        double gs = 0.0, gq = 0.0;
+        for (int c = g * cpg; c < (g + 1) * cpg; ++c) {
+            gs += chs[0][c];
+            gq += chs[1][c];
+        }
+        const double n = (double)cpg * L;
+        const double mean = gs / n;
+        const double var = fmax(gq / n - mean * mean, 0.0);
+        const double scale = (double)a.gamma[tid] / sqrt(var + 1e-5);
+        sc[tid] = (float)scale;
+        sh[tid] = (float)((double)a.beta[tid] - mean * scale);
+    }
+    __syncthreads();
+    const int c0 = (4 * tid) % C;
+    const float4 S = make_float4(sc[c0], sc[c0 + 1], sc[c0 + 2], sc[c0 + 3]);
+    const float4 H = make_float4(sh[c0], sh[c0 + 1], sh[c0 + 2], sh[c0 + 3]);
+    float4* out = (float4*)(a.out + b * L * C);
+    if (a.res) {
+        // the residual in groups of RC float4s, to stay within 128 registers
+        constexpr int RC = 4;
+        const float4* res = (const float4*)(a.res + b * L * C);
+#pragma unroll
+        for (int u0 = 0; u0 < R; u0 += RC) {
+            float4 r[RC];
+#pragma unroll
+            for (int u = 0; u < RC && u0 + u < R; ++u) r[u] = res[min(tid + NT * (u0 + u), n4 - 1)];
+#pragma unroll
+            for (int u = 0; u < RC && u0 + u < R; ++u) {
+                float4& x = v[u0 + u];
+                x = make_float4(fmaf(x.x, S.x, H.x) + r[u].x, fmaf(x.y, S.y, H.y) + r[u].y,
+                                fmaf(x.z, S.z, H.z) + r[u].z, fmaf(x.w, S.w, H.w) + r[u].w);
+            }
+        }
+    } else {
+#pragma unroll
+        for (int u = 0; u < R; ++u)
+            v[u] = make_float4(fmaf(v[u].x, S.x, H.x), fmaf(v[u].y, S.y, H.y), fmaf(v[u].z, S.z, H.z),
+                               fmaf(v[u].w, S.w, H.w));
+    }
+#pragma unroll
+    for (int u = 0; u < R; ++u) {
+        if (tid + NT * u < n4) {
+            float4 y = v[u];
+            if (a.relu) y = make_float4(fmaxf(y.x, 0.f), fmaxf(y.y, 0.f), fmaxf(y.z, 0.f), fmaxf(y.w, 0.f));
+            out[tid + NT * u] = y;
+        }
+    }
+}
+
 }  // namespace afm

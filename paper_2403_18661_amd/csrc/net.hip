@@ -672,7 +672,11 @@ void launch_gn(const af_net* net, const void* in, const void* res, void* out, si
     g.gamma = net->d_gn + gn_off;
     g.beta = g.gamma + C;
     g.L = L; g.C = C; g.G = net->gn_groups; g.relu = relu; g.pool = pool;
-    hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
+    constexpr int NT = 1024, R = 6;   // threads and float4s per thread of the register-resident form
+    if (!pool && (int64_t)L * C <= 4LL * NT * R)
+        hipLaunchKernelGGL((gn_reg_kernel<NT, R>), dim3((unsigned)nb), dim3(NT), 0, s, g);
+    else
+        hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
 }
 }
 
