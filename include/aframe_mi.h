@@ -171,7 +171,8 @@ af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n
  * two in [16, 256] divisible by groups; precision AF_F32, or AF_BF16_F32ACT
  * (BF16 conv operands, FP32 activations and GroupNorm); in_ch must be 2.
  * The handle works with af_score_windows, the timeslide entry points, the
- * autotuner and the profile; statistics are taken per window, so a window's
+ * streaming server, the autotuner and the profile; statistics are taken per
+ * window, so a window's
  * logit does not depend on its batch.  AF_EINVAL on a bad shape or length. */
 af_status af_net_create_gn(const af_net_desc* desc, int32_t groups, const double* params, int64_t n_params,
                            af_precision precision, af_net** out);

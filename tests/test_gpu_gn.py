@@ -111,3 +111,28 @@ def test_gn_rejects_unsupported_forms():
         P.Net(k7, make_params(k7, seed=59), "f32")
     with pytest.raises(P.AframeError, match="EINVAL"):
         P.Net(TINY_GN_ARCH, np.zeros(10), "f32")                   # params too short
+
+
+def test_gn_stream_equals_offline():
+    # the streaming server scores a GroupNorm net's windows as the offline path does
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from paper_2403_18661_amd.stream import Server
+    from synth.noise import coloured_noise
+    from tests.test_gpu_stream import run_stream
+    banner("gn stream vs offline")
+    fs = 2048
+    params = make_params(GN_ARCH, seed=60)
+    net = P.Net(GN_ARCH, params, "f32")
+    x = coloured_noise(fs * 84, seed=61)
+    srv = Server(net, max_streams=2, hbm_budget=4 << 30)
+    sid = srv.admit()
+    out = run_stream(srv, {sid: x}, lambda r: fs)[sid]
+    path = OfflinePath(net, x.shape[1], PathConfig(psd_len=64 * fs))
+    path.run(torch.from_numpy(x).cuda())
+    lg, ig = path.logits.cpu().numpy(), path.integrated.cpu().numpy()
+    n, m = len(out[0]), len(out[1])
+    assert n > 100 and m > 80 and n <= len(lg)
+    np.testing.assert_allclose(out[0], lg[:n], atol=1e-5)
+    np.testing.assert_allclose(out[1], ig[:m], atol=1e-5)
