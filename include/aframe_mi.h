@@ -172,8 +172,8 @@ af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n
  * (BF16 conv operands, FP32 activations and GroupNorm); in_ch must be 2.
  * The handle works with af_score_windows, the timeslide entry points, the
  * streaming server, the autotuner and the profile; statistics are taken per
- * window, so a window's
- * logit does not depend on its batch.  AF_EINVAL on a bad shape or length. */
+ * window, so a window's logit does not depend on its batch.  AF_EINVAL on a
+ * bad shape or length. */
 af_status af_net_create_gn(const af_net_desc* desc, int32_t groups, const double* params, int64_t n_params,
                            af_precision precision, af_net** out);
 void af_net_destroy(af_net* net);
