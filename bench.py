@@ -258,13 +258,13 @@ def inject_leg(args, P, log):
 
 
 def gn_bytes(arch, windows):
-    """Algorithmic HBM bytes of every GroupNorm launch over `windows` windows:
-    each reads its conv's FP32 output (and the residual) once and writes its
-    output once."""
-    c = arch.stem_ch
+    """Algorithmic HBM bytes of the GroupNorm launches of the blocks over
+    `windows` windows: each reads its conv's FP32 output (and the residual)
+    once and writes its output once.  (The stem's norm runs inside the stem
+    kernel for this workload and is timed with it.)"""
     l_conv = (arch.window + 2 * (arch.kernel // 2) - arch.kernel) // arch.stem_stride + 1
     L = (l_conv - 1) // 2 + 1 if arch.stem_pool else l_conv
-    b = l_conv * c + L * c
+    b = 0
     for _, _, c_out, stride, proj in arch.block_list():
         lo = (L - 1) // stride + 1
         b += 2 * lo * c_out                     # conv1: in place

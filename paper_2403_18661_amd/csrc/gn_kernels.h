@@ -44,6 +44,106 @@ __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a) {
     }
 }
 
+// The whole stem of the GroupNorm net in one pass, for 32-channel stems with a
+// max-pool whose raw output has a multiple of 64 rows, at most 32 MAXR: raw
+// conv -> GroupNorm -> ReLU -> max-pool k3 s2 p1, with the raw output held in
+// registers.  1024 threads: thread t keeps channel t % 32 of the R = L_conv / 32
+// consecutive rows of row block t / 32.  Statistics as in gn_reg_kernel (lanes
+// l and l xor 32 share a channel).  Pooled row p of a block takes its rows
+// 2p - 1 .. 2p + 1; the first of them for p = 0 is the previous block's last
+// row, passed through LDS (row -1 is padding: every candidate is >= 0, so 0
+// stands in for it).
+template <int NCH, int KW, int MAXR>
+__global__ void __launch_bounds__(1024) gn_stem_fused_kernel(StemArgs a, const float* gamma, const float* beta,
+                                                             int G) {
+    extern __shared__ float xs[];  // [n_ch][window]
+    __shared__ double part[2][16][32];
+    __shared__ double chs[2][32];
+    __shared__ float sc[32], sh[32], edge[32][32];
+    const int tid = threadIdx.x, c = tid & 31, rb = tid >> 5, lane = tid & 63, wv = tid >> 6;
+    const int b = blockIdx.x;
+    const WinAddr wa = window_addr(a, a.first_window + b);
+    if (tid < 256) stage_window(a, wa, xs);
+    const int W = a.window, R = a.L_conv / 32, r0 = rb * R;
+    float w[NCH][KW];
+#pragma unroll
+    for (int ci = 0; ci < NCH; ++ci)
+#pragma unroll
+        for (int j = 0; j < KW; ++j) w[ci][j] = a.w[(c * NCH + ci) * KW + j];
+    __syncthreads();
+    constexpr int pad = (KW - 1) / 2;
+    float v[MAXR];
+    double s = 0.0, q = 0.0;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        v[i] = 0.f;
+        if (i < R) {
+            const int q0 = (r0 + i) * a.s0 - pad;
+            float acc = 0.f;
+#pragma unroll
+            for (int ci = 0; ci < NCH; ++ci)
+#pragma unroll
+                for (int j = 0; j < KW; ++j) {
+                    const int p = q0 + j;
+                    const float x = (p >= 0 && p < W) ? xs[ci * W + p] : 0.f;
+                    acc = fmaf(w[ci][j], x, acc);
+                }
+            v[i] = acc;
+            s += (double)acc;
+            q += (double)acc * (double)acc;
+        }
+    }
+    s += __shfl_xor(s, 32);
+    q += __shfl_xor(q, 32);
+    if (lane < 32) {
+        part[0][wv][c] = s;
+        part[1][wv][c] = q;
+    }
+    __syncthreads();
+    if (tid < 32) {
+        double cs = 0.0, cq = 0.0;
+        for (int k = 0; k < 16; ++k) {
+            cs += part[0][k][tid];
+            cq += part[1][k][tid];
+        }
+        chs[0][tid] = cs;
+        chs[1][tid] = cq;
+    }
+    __syncthreads();
+    if (tid < 32) {
+        const int cpg = 32 / G, g = tid / cpg;
+        double gs = 0.0, gq = 0.0;
+        for (int cc = g * cpg; cc < (g + 1) * cpg; ++cc) {
+            gs += chs[0][cc];
+            gq += chs[1][cc];
+        }
+        const double n = (double)cpg * a.L_conv;
+        const double mean = gs / n;
+        const double var = fmax(gq / n - mean * mean, 0.0);
+        const double scale = (double)gamma[tid] / sqrt(var + 1e-5);
+        sc[tid] = (float)scale;
+        sh[tid] = (float)((double)beta[tid] - mean * scale);
+    }
+    __syncthreads();
+    const float S = sc[c], H = sh[c];
+    float last = 0.f;
+#pragma unroll
+    for (int i = 0; i < MAXR; ++i) {
+        v[i] = fmaxf(fmaf(v[i], S, H), 0.f);
+        if (i == R - 1) last = v[i];
+    }
+    edge[rb][c] = last;
+    __syncthreads();
+    const float prev = rb > 0 ? edge[rb - 1][c] : 0.f;
+    float* out = (float*)a.out + (size_t)b * a.L_out * 32;
+#pragma unroll
+    for (int j = 0; j < MAXR / 2; ++j)
+        if (2 * j < R) {
+            const float left = j == 0 ? prev : v[2 * j - 1];
+            out[(size_t)(rb * (R / 2) + j) * 32 + c] = fmaxf(fmaxf(left, v[2 * j]), v[2 * j + 1]);
+        }
+}
+
 struct GnArgs {
     const float* in;      // [B][L][C]
     const float* res;     // [B][L][C] added after the affine map, or null

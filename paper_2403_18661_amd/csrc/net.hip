@@ -793,7 +793,16 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             return hipPeekAtLastError() == hipSuccess && t_end();
         };
         if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
-        if (net->gn_groups) {
+        constexpr int STEM_MAXR = 48;
+        if (net->gn_groups && d.stem_ch == 32 && d.stem_pool && net->stem_lconv % 64 == 0 &&
+            net->stem_lconv / 32 <= STEM_MAXR) {
+            // conv, GroupNorm, ReLU and pool in one pass into X
+            sa.out = buf[BX];
+            hipLaunchKernelGGL((gn_stem_fused_kernel<2, 3, STEM_MAXR>), dim3(nb), dim3(1024), stem_lds, s, sa,
+                               (const float*)net->d_gn, (const float*)net->d_gn + 32, net->gn_groups);
+            AF_LAUNCHED();
+            t_end();
+        } else if (net->gn_groups) {
             // raw stem conv into R, then GroupNorm, ReLU (and pool) into X
             sa.out = buf[BR];
             hipLaunchKernelGGL((gn_stem_kernel<2, 3>), dim3(nb), dim3(256), stem_lds, s, sa);

@@ -24,9 +24,14 @@ def oracle_logits(params, arch, y, stride, nw, shifts=None, wrap=0):
     return oracle.net_forward_gn(params, arch, w)
 
 
+# a 480-sample window gives a 240-row stem, which the one-pass stem kernel does
+# not take (rows per thread block must be even): the two-kernel stem runs
+TINY480_GN_ARCH = dataclasses.replace(TINY_GN_ARCH, name="tiny480-gn", window=480)
+
+
 @pytest.mark.parametrize("arch,prec,nw", [(TINY_GN_ARCH, "f32", 37), (TINY_GN_ARCH, "bf16f", 37),
-                                          (GN_ARCH, "f32", 5), (GN_ARCH, "bf16f", 5)],
-                         ids=["tiny-f32", "tiny-bf16f", "resnet34-f32", "resnet34-bf16f"])
+                                          (TINY480_GN_ARCH, "f32", 9), (GN_ARCH, "f32", 5), (GN_ARCH, "bf16f", 5)],
+                         ids=["tiny-f32", "tiny-bf16f", "tiny480-f32", "resnet34-f32", "resnet34-bf16f"])
 def test_gn_net_matches_oracle(arch, prec, nw):
     P = need_gpu()
     banner(f"gn net {arch.name} {prec} nw={nw}")
