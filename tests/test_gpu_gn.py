@@ -141,3 +141,26 @@ def test_gn_stream_equals_offline():
     assert n > 100 and m > 80 and n <= len(lg)
     np.testing.assert_allclose(out[0], lg[:n], atol=1e-5)
     np.testing.assert_allclose(out[1], ig[:m], atol=1e-5)
+
+
+def test_gn_timeslide_graph_replays_match_direct_call():
+    # the GroupNorm launches capture into the timeslide graph: every replay,
+    # with eager work in between, gives the direct call's logits
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.timeslides import TimeslidePlan
+    banner("gn timeslide graph replay")
+    params = make_params(TINY_GN_ARCH, seed=62)
+    y = dev(series(6000, seed=63))
+    net = P.Net(TINY_GN_ARCH, params, "f32")
+    seg_off, seg_len, shifts = [0, 2500], [2500, 3500], [256 * k for k in range(1, 5)]
+    direct = P.score_timeslides(net, y, seg_off, seg_len, shifts, stride=128).cpu().numpy()
+    plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=128, graph=True)
+    assert plan.n_windows == len(direct) > 0
+    for _ in range(3):
+        plan.logits.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run()
+        plan.stream.synchronize()
+        np.testing.assert_array_equal(plan.logits[:plan.n_windows].cpu().numpy(), direct)
+        _ = (y * 2).sum().item()
