@@ -190,7 +190,8 @@ af_status af_net_set_fused(af_net* net, int enable);
 
 /* Number of timed layers: stem, each conv in execution order, GAP+FC head;
  * GroupNorm nets (af_net_create_gn) have one more, after the head, that
- * collects every GroupNorm launch (the stem's included). */
+ * collects the separate GroupNorm launches (every block's; the stem's only
+ * where it does not run inside the stem kernel, which is timed as layer 0). */
 int64_t af_net_n_layers(const af_net* net);
 /* Kernel timing (a tracing aid, Sec. VIII reports per-stage latencies).
  * Between begin and end, every af_score_windows call on this net records a HIP

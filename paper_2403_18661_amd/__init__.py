@@ -212,7 +212,7 @@ class Net:
     def profile_end(self):
         """Stop timing; return per-layer dict arrays ms, launches, flops
         (layer 0 = stem, then convs in execution order, then the head; GroupNorm
-        nets end with one more entry, every GroupNorm launch)."""
+        nets end with one more entry, the separate GroupNorm launches)."""
         n = self.n_layers
         ms = np.zeros(n)
         la = np.zeros(n, dtype=np.int64)
