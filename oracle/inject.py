@@ -18,7 +18,9 @@ basis gives F+ = 1, Fx = 0 (and |Fx| = 1 at psi = pi/4); F+^2 + Fx^2 does not
 depend on psi and F(psi + pi/2) = -F(psi); the H1-L1 delay difference never
 exceeds the baseline light time (about 10 ms, Sec. IX) and reaches it along
 the baseline; whole-sample delays shift exactly; the SNR of a sinusoid on a
-frequency bin against a flat PSD has the closed form A^2 N / (fs S).
+frequency bin against a flat PSD has the closed form A^2 N / (fs S); against a
+PSD given on a coarser grid, S at each sinusoid is the linear interpolation of
+its two grid neighbours.
 """
 import numpy as np
 

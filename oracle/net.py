@@ -23,6 +23,9 @@ than the plain FP64 tolerance does.
 Pins (tests/test_oracle_net.py): conv1d == brute-force loops and == torch's
 float64 conv1d; folded == unfolded BatchNorm; the whole forward == a torch.nn
 float64 model built from the same parameters; FLOP counts of both architectures.
+The rounding points of net_forward_quant (tests/test_oracle_quant_points.py):
+hand-worked logits of one-channel networks whose values sit on or between BF16
+grid points, so that moving any rounding point changes a logit.
 """
 import numpy as np
 from numpy.lib.stride_tricks import sliding_window_view

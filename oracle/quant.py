@@ -11,9 +11,10 @@ Written from the formats' definitions, on float64 inputs:
   448 = 1.75 * 2^8, smallest normal 2^-6 and subnormal step 2^-9.  Rounding is
   to nearest even and saturates at +-448.
 
-Pins (tests/test_oracle_quant.py): torch's own float -> bfloat16 and
+Pins (tests/test_oracle_post.py): torch's own float -> bfloat16 and
 float -> float8_e4m3fn casts on exactly representable float32 inputs, the
-format's listed extreme values, and hand-checked ties.
+format's listed extreme values (tests/golden/e4m3_points.txt), and
+hand-checked ties (tests/test_oracle_quant_points.py).
 """
 import numpy as np
 

@@ -17,9 +17,11 @@ equal to the pass-band fraction (1 - 2 f_hp / fs).  With a rolling PSD the
 output sample n uses the filter of the hop that contains it.
 
 Pins (tests/test_oracle_whiten.py): white noise -> x / sigma exactly; the
-exact-inverse identity with an untruncated analytic ASD; output variance equal
-to the band fraction; scale invariance; direct sum == FFT convolution ==
-per-sample dot products.
+exact inverse for an ASD whose inverse is a short cosine sum (noise coloured by
+the exact inverse of the resulting filter comes back as sqrt(2/fs) times the
+white input at every output sample); taps equal the written-out cosine sum;
+output variance equal to the band fraction; scale invariance; direct sum ==
+FFT convolution == per-sample dot products.
 """
 import numpy as np
 import scipy.signal

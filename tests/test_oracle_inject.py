@@ -73,3 +73,24 @@ def test_snr_of_a_sinusoid_on_a_bin():
     rho2 = oracle.network_snr(sig, psd, FS / 8192, FS, 20.0)[0]
     assert rho2 == pytest.approx(np.sqrt(2) * rho, rel=1e-12)
     assert oracle.network_snr(sig, psd, FS / 8192, FS, m * FS / n + 1)[0] < 1e-9 * rho   # below f_low
+
+
+def test_snr_interpolates_a_non_flat_psd_linearly():
+    # PSD given every 1.5 Hz with unrelated values per grid point; sinusoids on
+    # the 0.5 Hz bins of a 2 s series at 150.5 Hz and 302 Hz fall one third of
+    # the way from a grid point to the next, so S there is (2/3) S_k + (1/3) S_k+1,
+    # and one at 301.5 Hz falls on grid point 201.  Each contributes A^2 N / (fs S)
+    # to rho^2.  Nearest-grid, swapped-weight or shifted-index readings all differ.
+    n, df = 4096, 1.5
+    rng = np.random.default_rng(7)
+    psd = rng.uniform(1e-3, 3e-3, (2, 700))
+    t = np.arange(n) / FS
+    sig = np.zeros((1, 2, n))
+    amps = {(0, 301): 1.3, (0, 604): 0.7, (1, 603): 2.1}
+    for (d, m), a in amps.items():
+        sig[0, d] += a * np.cos(2 * np.pi * m * FS / n * t)
+    s1 = (2 * psd[0, 100] + psd[0, 101]) / 3            # 150.5 Hz between 150.0 and 151.5
+    s2 = (2 * psd[0, 201] + psd[0, 202]) / 3            # 302.0 Hz between 301.5 and 303.0
+    s3 = psd[1, 201]                                    # 301.5 Hz on the grid
+    rho2 = n / FS * (1.3 ** 2 / s1 + 0.7 ** 2 / s2 + 2.1 ** 2 / s3)
+    assert oracle.network_snr(sig, psd, df, FS, 20.0)[0] == pytest.approx(np.sqrt(rho2), rel=1e-10)

@@ -92,3 +92,25 @@ def test_piecewise_single_hop_equals_plain_and_hops_switch():
     yq = oracle.whiten_piecewise(x, psd2, FS, n0=1024, n_out=n - 2048, psd_hop=16384)
     np.testing.assert_allclose(yq[:, :16384], y[:, :16384], atol=1e-9)
     np.testing.assert_allclose(yq[:, 16384:], 0.5 * y[:, 16384:], atol=1e-9)
+
+
+def test_exact_inverse_of_a_short_cosine_sum_asd():
+    # An inverse ASD A(f) = a + 2 b1 cos(2 pi f/fs) + 2 b5 cos(10 pi f/fs) has the
+    # impulse response q[0] = a, q[+-1] = b1, q[+-5] = b5 and nothing else, so the
+    # truncated filter is h[0] = a, h[+-1] = b1 t(1), h[+-5] = b5 t(5) with the
+    # taper t(m) = (1 + cos(pi m / M)) / 2.  Noise coloured by the exact inverse
+    # of that filter (division by its transfer function on a periodic grid) is
+    # whitened back to sqrt(2/fs) times the white input at every output sample.
+    fs, L, N = 2048.0, 4096, 1 << 15
+    a, b1, b5 = 1.0, 0.2, -0.15
+    M = 1024
+    t = lambda m: 0.5 * (1.0 + np.cos(np.pi * m / M))
+    f = np.arange(L // 2 + 1) * fs / L
+    A = a + 2 * b1 * np.cos(2 * np.pi * f / fs) + 2 * b5 * np.cos(10 * np.pi * f / fs)
+    psd = np.tile(1.0 / A ** 2, (2, 1))
+    z = np.random.default_rng(11).standard_normal((2, N))
+    w = 2 * np.pi * np.arange(N // 2 + 1) / N
+    G = a + 2 * b1 * t(1) * np.cos(w) + 2 * b5 * t(5) * np.cos(5 * w)
+    x = np.fft.irfft(np.fft.rfft(z, axis=-1) / G, n=N, axis=-1)
+    y = oracle.whiten(x, psd, fs, highpass=0.0, fduration=1.0)
+    np.testing.assert_allclose(y, np.sqrt(2.0 / fs) * z[:, M:N - M], rtol=0, atol=1e-12)
