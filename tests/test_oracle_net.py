@@ -112,6 +112,7 @@ def torch_model(arch, params):
         with torch.no_grad():
             h = model["blocks"](model["stem"](torch.from_numpy(x)))
             return model["fc"](h.mean(dim=2))[:, 0].numpy()
+    run.model = model
     return run
 
 
