@@ -405,6 +405,11 @@ def main():
     integ = {}
     for prec in args.precisions.split(","):
         net = P.Net(arch, params, prec)
+        if prec == "fp8":
+            # bias correction of the E4M3 weights on 64 windows of unit-variance
+            # noise (the statistics of whitened strain), outside the timed region
+            c = np.random.default_rng(99).standard_normal((2, 3072 + 1000 * 63)).astype(np.float32)
+            net.calibrate(torch.from_numpy(c).cuda(), 1000)
         path = OfflinePath(net, x.shape[1], cfg, batch=args.batch)
         if not args.no_autotune:
             changed = net.autotune(batch=min(args.batch, 2048), ws=path.ws_net)

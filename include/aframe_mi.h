@@ -176,6 +176,27 @@ af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n
  * bad shape or length. */
 af_status af_net_create_gn(const af_net_desc* desc, int32_t groups, const double* params, int64_t n_params,
                            af_precision precision, af_net** out);
+/* Bias correction of an AF_FP8 net from calibration windows (E4M3 weight
+ * rounding moves each conv's output by the same amount on every window: the
+ * weight error times the mean of the conv's input; that systematic shift, not
+ * the per-window rounding noise, is most of the FP8 logit error of a deep
+ * net).  The windows of y (as for af_score_windows without shifts: window i
+ * starts at i*stride; noise of the statistics the net will see, e.g. whitened
+ * noise) are scored by the same network in FP32, whose activations give mu,
+ * the mean of every conv input per channel over windows and time.  Each conv
+ * bias b' becomes b' - sum_{c,j} (s e4m3(W'/s) - W')[o][c][j] mu[c] (FP64 on
+ * the host, from the weights as created), then the FC bias is lowered by the
+ * mean, over the calibration windows, of (FP8 logit - FP32 logit) with the
+ * corrected convs.  The result depends only on the calibration windows
+ * (calling again recomputes from the created weights).  Synchronous: it
+ * waits for the device, allocates its own scratch and replaces the biases in
+ * place, so graphs captured with this net replay with the new biases; work
+ * queued with the net on other streams must be complete.  ws must hold at
+ * least af_score_workspace_bytes() of the FP32 form for one window (twice
+ * that of the FP8 net); windows run in passes of what it holds.  AF_EINVAL
+ * for a net that is not FP8 (GroupNorm nets included) or windows past n. */
+af_status af_net_calibrate(af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n, int64_t stride,
+                           int64_t n_windows, void* ws, size_t ws_bytes, af_stream stream);
 void af_net_destroy(af_net* net);
 /* Total conv + FC multiply-accumulates per window. */
 int64_t af_net_macs(const af_net* net);
@@ -220,7 +241,10 @@ af_status af_net_layer_tile(const af_net* net, int64_t layer, int32_t* mt, int32
 /* Use tile candidate `chosen` (0 <= chosen < n_candidates) for conv layer
  * `layer`, e.g. to replay an earlier autotuning without timing again.  Waits
  * for the device, then rebuilds the layer's weight image; logits are the same
- * bit for bit under every candidate.  AF_EINVAL for a bad layer or index. */
+ * bit for bit under every candidate.  AF_EINVAL for a bad layer or index.
+ * A replaced weight image (here or in af_net_autotune) stays allocated until
+ * af_net_destroy, so a graph captured before the switch still replays with
+ * the old tile and image, giving the same logits. */
 af_status af_net_set_layer_tile(af_net* net, int64_t layer, int32_t chosen);
 
 /* Workspace needed to score `batch` windows per internal pass. */

@@ -247,6 +247,17 @@ class Net:
     def workspace_bytes(self, batch):
         return lib().af_score_workspace_bytes(self._h, batch)
 
+    def calibrate(self, y, stride, n_windows=None, batch=256, stream=None):
+        """Bias correction of an FP8 net from the windows of y [n_ch, n]
+        float32 (af_net_calibrate; synchronous)."""
+        _check_dev(y, "y", (torch.float32,))
+        n_ch, n = y.shape
+        if n_windows is None:
+            n_windows = (n - self.window) // stride + 1
+        ws = _workspace(2 * self.workspace_bytes(max(1, min(batch, n_windows))), y.device)
+        check(lib().af_net_calibrate(self._h, _ptr(y), n_ch, y.stride(0), n, stride, n_windows, _ptr(ws),
+                                     ws.numel(), _stream(stream)))
+
     def score_windows(self, y, stride, n_windows=None, shifts=None, wrap=0, batch=1024, out=None, ws=None,
                       stream=None):
         """Logits of windows of y [n_ch, n] float32 (af_score_windows)."""

@@ -42,6 +42,7 @@ SIGNATURES = {
     "af_net_create": (c_int, [ctypes.POINTER(NetDesc), c_vp, c_i64, c_int, ctypes.POINTER(c_vp)]),
     "af_net_create_gn": (c_int, [ctypes.POINTER(NetDesc), ctypes.c_int32, c_vp, c_i64, c_int, ctypes.POINTER(c_vp)]),
     "af_net_destroy": (None, [c_vp]),
+    "af_net_calibrate": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "af_net_macs": (c_i64, [c_vp]),
     "af_score_workspace_bytes": (c_sz, [c_vp, c_i64]),
     "af_net_n_layers": (c_i64, [c_vp]),

@@ -1,5 +1,6 @@
 // Scoring network: creation (BatchNorm folding, precision conversion, device
 // layouts), execution plan and the af_score_windows entry point.
+#include <algorithm>
 #include <cfenv>
 #include <cmath>
 #include <cstring>
@@ -299,7 +300,13 @@ struct af_net {
     float* d_b = nullptr;      // conv biases
     float* d_ws = nullptr;     // FP8 per-output-channel scales
     float* d_stem = nullptr;   // stem weights [C][in][k] then bias [C]
-    float* d_fc = nullptr;     // fc weights [C_last]
+    float* d_fc = nullptr;     // fc weights [C_last], then the fc bias
+    std::vector<double> bias64;        // folded conv biases (FP64), as created
+    double fc_b64 = 0.0;               // fc bias as created
+    std::vector<double> params_host;   // FP8 nets: the creation parameters (for calibration)
+    double* d_tap = nullptr;           // calibration: per-conv input channel sums [ops][tap_pitch]
+    int tap_pitch = 0;
+    std::vector<void*> retired;        // weight images replaced by a tile switch (kept for captured graphs)
     int gn_groups = 0;         // > 0: GroupNorm net (stem's gamma, beta first in d_gn)
     float* d_gn = nullptr;     // GroupNorm gamma [C], beta [C] per norm layer
     // kernel timing (af_net_profile_begin/end): one event pair per launch
@@ -336,6 +343,7 @@ void free_net(af_net* n) {
     drop_records(n);
     for (ConvOp& op : n->ops)
         if (op.d_img) (void)hipFree(op.d_img);
+    for (void* r : n->retired) (void)hipFree(r);
     if (n->d_b) (void)hipFree(n->d_b);
     if (n->d_ws) (void)hipFree(n->d_ws);
     if (n->d_stem) (void)hipFree(n->d_stem);
@@ -457,6 +465,7 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
         set_tiling(op);
         wfold.insert(wfold.end(), w.begin(), w.end());
         for (int o = 0; o < c_out; ++o) bias.push_back((float)b[o]);
+        net->bias64.insert(net->bias64.end(), b.begin(), b.end());
         net->macs += (int64_t)op.l_out * c_out * c_in * kw;
         net->layer_macs.push_back((int64_t)op.l_out * c_out * c_in * kw);
         net->act_elems = std::max<int64_t>(net->act_elems, (int64_t)op.l_out * c_out);
@@ -507,10 +516,18 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
         set_error("params length mismatch: %lld left for an FC of %d inputs", (long long)(p_end - p), C);
         return AF_EINVAL;
     }
-    if (256 % C != 0) { free_net(net); set_error("last width must divide 256"); return AF_EINVAL; }
-    std::vector<float> fc(C);
-    for (int c = 0; c < C; ++c) fc[c] = (float)p[c];
+    if (256 % C != 0 && C % 256 != 0) {
+        free_net(net);
+        set_error("last width must divide 256 or be a multiple of it");
+        return AF_EINVAL;
+    }
+    std::vector<float> fc(C + 1);
+    for (int c = 0; c <= C; ++c) fc[c] = (float)p[c];   // weights, then the bias
     net->fc_b = (float)p[C];
+    net->fc_b64 = p[C];
+    net->tap_pitch = 1;
+    for (const ConvOp& op : net->ops) net->tap_pitch = std::max(net->tap_pitch, op.c_in);
+    if (prec == AF_FP8) net->params_host.assign(params, params + n_params);
     net->macs += C;
     net->layer_macs.push_back(C);
     if (groups) net->layer_macs.push_back(0);   // every GroupNorm launch, timed as one more layer
@@ -840,6 +857,10 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             a.wpt = op.wpt;
             a.tt = op.tt;
             a.tiles_per_win = op.tiles_per_win;
+            if (net->d_tap)   // calibration of an FP8 net: this FP32 net's conv input sums
+                hipLaunchKernelGGL(channel_sum_kernel, dim3((unsigned)op.c_in), dim3(256), 0, s,
+                                   (const float*)buf[op.in_buf], (int64_t)nb * op.l_in, op.c_in,
+                                   net->d_tap + (size_t)(layer - 1) * net->tap_pitch);
             if (!t_begin(layer, nb)) { set_error("profiling event failed"); return AF_EHIP; }
             op.cfg.fn(a, s);
             AF_LAUNCHED();
@@ -852,9 +873,11 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         }
         if (!t_begin(layer + 1, nb)) { set_error("profiling event failed"); return AF_EHIP; }
         if (act_size(net->prec) == 4)
-            hipLaunchKernelGGL(gap_fc_kernel<PF32>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);
+            hipLaunchKernelGGL(gap_fc_kernel<PF32>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C,
+                               (const float*)net->d_fc, logits + w0);
         else
-            hipLaunchKernelGGL(gap_fc_kernel<PBF16>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C, net->d_fc, net->fc_b, logits + w0);
+            hipLaunchKernelGGL(gap_fc_kernel<PBF16>, dim3(nb), dim3(256), 0, s, buf[BX], net->last_L, net->last_C,
+                               (const float*)net->d_fc, logits + w0);
         AF_LAUNCHED();
         t_end();
     }
@@ -1007,7 +1030,9 @@ af_status switch_candidate(af_net* net, ConvOp& op, int idx) {
         set_error("weight image upload failed");
         return AF_ENOMEM;
     }
-    (void)hipFree(op.d_img);
+    // a graph captured earlier may still launch the old image with the old
+    // tiling (the same logits bit for bit): keep it until the net is destroyed
+    net->retired.push_back(op.d_img);
     next.d_img = d_img;
     op = next;
     return AF_OK;
@@ -1165,4 +1190,107 @@ extern "C" af_status af_net_profile_end(af_net* net, int64_t n_layers, double* m
     }
     drop_records(net);
     return AF_OK;
+}
+
+extern "C" af_status af_net_calibrate(af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
+                                      int64_t stride, int64_t n_windows, void* ws, size_t ws_bytes,
+                                      af_stream stream) {
+    clear_error();
+    AF_CHECK_ARG(net && y && ws, "net, y and ws must be non-null");
+    AF_CHECK_ARG(net->prec == AF_FP8 && !net->gn_groups && !net->params_host.empty(),
+                 "calibration applies to FP8 nets");
+    AF_CHECK_ARG(n_ch == net->desc.in_ch, "n_ch %lld does not match the net's %d inputs", (long long)n_ch,
+                 net->desc.in_ch);
+    AF_CHECK_ARG(n >= 1 && ld_y >= n && stride >= 1 && n_windows >= 1 && n_windows < (1LL << 24),
+                 "need n >= 1, ld_y >= n, stride >= 1, 1 <= n_windows < 2^24");
+    AF_CHECK_ARG((n_windows - 1) * stride + net->desc.window <= n, "calibration window %lld ends past n = %lld",
+                 (long long)(n_windows - 1), (long long)n);
+    int dev = -1;
+    (void)hipGetDevice(&dev);
+    AF_CHECK_ARG(dev == net->device, "net was created on device %d, current device is %d", net->device, dev);
+    hipStream_t s = (hipStream_t)stream;
+
+    // the same network in FP32: its activations give the conv input means and
+    // its logits the reference of the FC shift
+    af_net* twin = nullptr;
+    af_status st = create_net(&net->desc, 0, net->params_host.data(), (int64_t)net->params_host.size(), AF_F32,
+                              &twin);
+    if (st != AF_OK) return st;
+    double* d_tap = nullptr;
+    float* d_l = nullptr;
+    auto done = [&](af_status r) {
+        if (d_tap) (void)hipFree(d_tap);
+        if (d_l) (void)hipFree(d_l);
+        free_net(twin);
+        return r;
+    };
+    if (ws_bytes < af_score_workspace_bytes(twin, 1)) {
+        set_error("workspace too small: calibration needs at least %zu bytes", af_score_workspace_bytes(twin, 1));
+        return done(AF_EINVAL);
+    }
+    const size_t pitch = (size_t)twin->tap_pitch, n_tap = net->ops.size() * pitch;
+    if (hipMalloc(&d_tap, n_tap * sizeof(double)) != hipSuccess ||
+        hipMalloc(&d_l, 2 * (size_t)n_windows * sizeof(float)) != hipSuccess) {
+        set_error("device allocation for calibration failed");
+        return done(AF_ENOMEM);
+    }
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((2 * n_tap + 255) / 256)), dim3(256), 0, s,
+                       (uint32_t*)d_tap, (int64_t)(2 * n_tap), 0u);
+    int64_t zero[4] = {0, 0, 0, 0};
+    twin->d_tap = d_tap;
+    st = score_batches(twin, y, ld_y, n, stride, n_windows, zero, 0, nullptr, 0, d_l, ws, ws_bytes, s);
+    twin->d_tap = nullptr;
+    if (st != AF_OK) return done(st);
+    std::vector<double> sums(n_tap);
+    if (hipMemcpyAsync(sums.data(), d_tap, n_tap * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("calibration: reading the input sums failed");
+        return done(AF_EHIP);
+    }
+
+    // each conv's bias less (W_q - W') mu, FP64, from the weights as created
+    std::vector<float> bias(net->bias64.size());
+    for (size_t k = 0; k < net->ops.size(); ++k) {
+        const ConvOp& op = net->ops[k];
+        const double cnt = (double)n_windows * op.l_in;
+        for (int o = 0; o < op.c_out; ++o) {
+            const double sc = net->wscale[op.b_off + o];
+            double shift = 0.0;
+            for (int j = 0; j < op.kw; ++j)
+                for (int c = 0; c < op.c_in; ++c) {
+                    const double w = net->wfold[op.w_off + ((size_t)o * op.kw + j) * op.c_in + c];
+                    const double q = std::min(448.0, std::max(-448.0, round_sig(w / sc, 4, -6, -9)));
+                    shift += (q * sc - w) * (sums[k * pitch + c] / cnt);
+                }
+            bias[op.b_off + o] = (float)(net->bias64[op.b_off + o] - shift);
+        }
+    }
+    const int C = net->last_C;
+    float fcb = (float)net->fc_b64;
+    // work already queued with this net on other streams reads the old biases
+    if (hipDeviceSynchronize() != hipSuccess ||
+        hipMemcpy(net->d_b, bias.data(), bias.size() * sizeof(float), hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemcpy(net->d_fc + C, &fcb, sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("calibration: bias upload failed");
+        return done(AF_EHIP);
+    }
+    // then the FC bias less the mean logit shift that remains
+    st = score_batches(net, y, ld_y, n, stride, n_windows, zero, 0, nullptr, 0, d_l + n_windows, ws, ws_bytes, s);
+    if (st != AF_OK) return done(st);
+    std::vector<float> l(2 * (size_t)n_windows);
+    if (hipMemcpyAsync(l.data(), d_l, l.size() * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        set_error("calibration: reading the logits failed");
+        return done(AF_EHIP);
+    }
+    double d = 0.0;
+    for (int64_t i = 0; i < n_windows; ++i) d += (double)l[n_windows + i] - (double)l[i];
+    d /= (double)n_windows;
+    fcb = (float)(net->fc_b64 - d);
+    if (hipMemcpy(net->d_fc + C, &fcb, sizeof(float), hipMemcpyHostToDevice) != hipSuccess) {
+        set_error("calibration: bias upload failed");
+        return done(AF_EHIP);
+    }
+    net->fc_b = fcb;
+    return done(AF_OK);
 }

@@ -1084,45 +1084,85 @@ __global__ void __launch_bounds__(256) stem_mfma_kernel(StemArgs a) {
     }
 }
 
-// Global average pool over time, then FC to one logit.  One workgroup per window.
+// Global average pool over time, then FC to one logit.  One workgroup of 256
+// threads per window.  fc holds the C weights, then the bias.  A width C that
+// divides 256 gives each channel 256 / C threads that stride over time; a
+// width that is a multiple of 256 gives each thread C / 256 channels.  The
+// FC products are reduced by wavefront shuffles, then across the four waves,
+// always in the same order.
 template <typename P>
-__global__ void __launch_bounds__(256) gap_fc_kernel(const void* act, int L, int C, const float* fc_w,
-                                                    float fc_b, float* logits) {
+__global__ void __launch_bounds__(256) gap_fc_kernel(const void* act, int L, int C, const float* fc,
+                                                    float* logits) {
     using Act = typename P::Act;
     __shared__ float part[256];
-    const int b = blockIdx.x;
+    __shared__ float wpart[4];
+    const int b = blockIdx.x, tid = threadIdx.x;
     const Act* x = (const Act*)act + (size_t)b * L * C;
-    // thread -> channel c = tid % C, time stride 256 / C (C divides 256)
-    const int per = 256 / C;
-    const int c = threadIdx.x % C, t0 = threadIdx.x / C;
-    // sixteen loads in flight per step (a clamped index past the end reads a
-    // valid element that then adds an exact zero), summed in time order
-    constexpr int U = 16;
-    float s = 0.f;
-    for (int t = t0; t < L; t += per * U) {
-        float v[U];
+    constexpr int U = 16;   // loads in flight per step
+    float prod = 0.f;
+    if (C <= 256) {
+        const int per = 256 / C;
+        const int c = tid % C, t0 = tid / C;
+        float s = 0.f;
+        for (int t = t0; t < L; t += per * U) {
+            float v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int tu = t + u * per;
-            const float e = act_to_f32<P>(x[(size_t)(tu < L ? tu : L - 1) * C + c]);
-            v[u] = tu < L ? e : 0.f;
+            for (int u = 0; u < U; ++u) {
+                // a clamped index past the end reads a valid element that then adds an exact zero
+                const int tu = t + u * per;
+                const float e = act_to_f32<P>(x[(size_t)(tu < L ? tu : L - 1) * C + c]);
+                v[u] = tu < L ? e : 0.f;
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) s += v[u];
         }
+        part[tid] = s;
+        __syncthreads();
+        if (tid < C) {
+            float tot = 0.f;
+            for (int k = 0; k < per; ++k) tot += part[k * C + tid];
+            prod = tot / (float)L * fc[tid];
+        }
+    } else {
+        for (int c = tid; c < C; c += 256) {
+            float s = 0.f;
+            for (int t = 0; t < L; t += U) {
+                float v[U];
 #pragma unroll
-        for (int u = 0; u < U; ++u) s += v[u];
+                for (int u = 0; u < U; ++u) {
+                    const int tu = t + u;
+                    const float e = act_to_f32<P>(x[(size_t)(tu < L ? tu : L - 1) * C + c]);
+                    v[u] = tu < L ? e : 0.f;
+                }
+#pragma unroll
+                for (int u = 0; u < U; ++u) s += v[u];
+            }
+            prod += s / (float)L * fc[c];
+        }
     }
-    part[threadIdx.x] = s;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) prod += __shfl_xor(prod, off);
+    if ((tid & 63) == 0) wpart[tid >> 6] = prod;
     __syncthreads();
-    if (threadIdx.x < C) {
-        float tot = 0.f;
-        for (int k = 0; k < per; ++k) tot += part[k * C + threadIdx.x];
-        part[threadIdx.x] = tot / (float)L * fc_w[threadIdx.x];
-    }
+    if (tid == 0) logits[b] = fc[C] + ((wpart[0] + wpart[1]) + (wpart[2] + wpart[3]));
+}
+
+// Per-channel sums of a [rows][C] FP32 tensor added into out[C] (FP64, one
+// workgroup per channel, a fixed summation order).  Used to take the conv
+// input means of a network during calibration.
+__global__ void __launch_bounds__(256) channel_sum_kernel(const float* __restrict__ in, int64_t rows, int C,
+                                                          double* __restrict__ out) {
+    __shared__ double part[256];
+    const int c = blockIdx.x, tid = threadIdx.x;
+    double s = 0.0;
+    for (int64_t r = tid; r < rows; r += 256) s += (double)in[r * C + c];
+    part[tid] = s;
     __syncthreads();
-    if (threadIdx.x == 0) {
-        float z = fc_b;
-        for (int k = 0; k < C; ++k) z += part[k];
-        logits[b] = z;
+    for (int o = 128; o > 0; o >>= 1) {
+        if (tid < o) part[tid] += part[tid + o];
+        __syncthreads();
     }
+    if (tid == 0) out[c] += part[0];
 }
 
 __global__ void fill_u32_kernel(uint32_t* p, int64_t n, uint32_t v) {

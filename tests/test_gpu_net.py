@@ -22,24 +22,38 @@ def series(n, seed, n_ch=2):
     return np.random.default_rng(seed).standard_normal((n_ch, n)).astype(np.float32)
 
 
-def oracle_logits(params, arch, y, stride, nw, shifts=None, wrap=0, precision=None):
+# calibration windows of FP8 nets: 16 windows of unit-variance noise (the
+# statistics of whitened strain), not the windows under test
+CALIB_STRIDE = 1000
+
+
+def calib_series(window=3072, n=16):
+    return series(window + CALIB_STRIDE * (n - 1), seed=99)
+
+
+def calib_windows(window=3072, n=16):
+    return oracle.unfold_windows(calib_series(window, n).astype(np.float64), window, CALIB_STRIDE)[:n]
+
+
+def oracle_logits(params, arch, y, stride, nw, shifts=None, wrap=0, precision=None, calib=False):
     w = oracle.unfold_windows(y.astype(np.float64), arch.window, stride, shifts, wrap)[:nw]
     if precision in (None, "f32"):
         return oracle.net_forward(params, arch, w)
-    return oracle.net_forward_quant(params, arch, w, precision)
+    return oracle.net_forward_quant(params, arch, w, precision,
+                                    calib=calib_windows(arch.window) if calib else None)
 
 
-FP8_RESNET = pytest.param(
-    RESNET_ARCH, "fp8", id="resnet-fp8",
-    marks=pytest.mark.xfail(strict=False, reason=(
-        "E4M3 operands carry ~3% relative rounding noise per conv; over the 36 convs of the "
-        "random-init ResNet the logit error reaches ~0.15 (measured on MI355X), above the 1e-1 "
-        "target; test_fp8_resnet_error_bound holds the measured level")))
+def make_net(P, arch, params, prec):
+    """A scoring net; FP8 nets are bias-corrected on the calibration windows."""
+    net = P.Net(arch, params, prec)
+    if prec == "fp8":
+        net.calibrate(dev(calib_series(arch.window)), CALIB_STRIDE)
+    return net
 
 
 @pytest.mark.parametrize("arch,prec", [(TINY_ARCH, "f32"), (TINY_ARCH, "bf16"), (TINY_ARCH, "bf16f"),
                                        (TINY_ARCH, "fp8"), (RESNET_ARCH, "f32"), (RESNET_ARCH, "bf16"),
-                                       (RESNET_ARCH, "bf16f"), FP8_RESNET],
+                                       (RESNET_ARCH, "bf16f"), (RESNET_ARCH, "fp8")],
                          ids=["tiny-f32", "tiny-bf16", "tiny-bf16f", "tiny-fp8", "resnet-f32", "resnet-bf16",
                               "resnet-bf16f", "resnet-fp8"])
 def test_logits_vs_fp64(arch, prec):
@@ -49,14 +63,14 @@ def test_logits_vs_fp64(arch, prec):
     nw = 12 if arch is RESNET_ARCH else 24
     stride = 128
     y = series(arch.window + stride * (nw - 1) + 77, seed=1)
-    net = P.Net(arch, params, prec)
+    net = make_net(P, arch, params, prec)
     got = net.score_windows(dev(y), stride, nw, batch=5).cpu().numpy()
     ref = oracle_logits(params, arch, y, stride, nw)
     err = np.abs(got - ref).max()
     print(f"max|dlogit| {prec} {arch.name}: {err:.3e}")
     assert err < TOL[prec]
     if prec != "f32":
-        emu = oracle_logits(params, arch, y, stride, nw, precision=prec)
+        emu = oracle_logits(params, arch, y, stride, nw, precision=prec, calib=prec == "fp8")
         e2 = np.abs(got - emu).max()
         print(f"max|dlogit| vs emulation: {e2:.3e}")
         # The emulation takes every rounding decision at the same points as the
@@ -121,15 +135,30 @@ def test_deterministic_across_batches():
     np.testing.assert_array_equal(a, b)
 
 
-def test_fp8_resnet_error_bound():
-    # regression bound for the measured FP8 ResNet error (see the xfail above)
+def test_fp8_calibration():
+    # bias correction on the GPU (FP32 twin for the input means and the FC
+    # shift) against the oracle's (FP64 net), on a shallow net the emulation
+    # pins tightly; repeated calibration gives the same logits bit for bit;
+    # only FP8 nets calibrate
     P = need_gpu()
-    banner("score resnet fp8 bound")
-    params = make_params(RESNET_ARCH, seed=0)
-    y = series(3072 + 128 * 11 + 77, seed=1)
-    got = P.Net(RESNET_ARCH, params, "fp8").score_windows(dev(y), 128, 12).cpu().numpy()
-    ref = oracle_logits(params, RESNET_ARCH, y, 128, 12)
-    assert np.abs(got - ref).max() < 0.3
+    banner("fp8 calibration")
+    arch = SHALLOW[1]
+    params = make_params(arch, seed=25)
+    y = series(3072 + 128 * 7, seed=26)
+    net = P.Net(arch, params, "fp8")
+    plain = net.score_windows(dev(y), 128).cpu().numpy()
+    net.calibrate(dev(calib_series()), CALIB_STRIDE)
+    got = net.score_windows(dev(y), 128).cpu().numpy()
+    emu = oracle_logits(params, arch, y, 128, len(got), precision="fp8", calib=True)
+    emu_plain = oracle_logits(params, arch, y, 128, len(got), precision="fp8")
+    print(f"calibrated vs emulation {np.abs(got - emu).max():.2e}; the correction moves the logits by "
+          f"{np.abs(emu - emu_plain).max():.2e} (GPU {np.abs(got - plain).max():.2e})")
+    assert np.abs(got - emu).max() < 2e-3
+    net.calibrate(dev(calib_series()), CALIB_STRIDE)
+    np.testing.assert_array_equal(net.score_windows(dev(y), 128).cpu().numpy(), got)
+    for prec in ("f32", "bf16", "bf16f"):
+        with pytest.raises(P.AframeError, match="EINVAL"):
+            P.Net(arch, params, prec).calibrate(dev(calib_series()), CALIB_STRIDE)
 
 
 def test_fused_tiny_matches_layer_path():
@@ -207,7 +236,11 @@ SHALLOW = [NetArch("shallow32", 2, 32, 7, 2, True, (32,), (1,)),
            NetArch("shallow128", 2, 32, 7, 2, True, (32, 64, 128), (1, 1, 1))]
 
 
-@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("bf16f", 2e-4), ("fp8", 5e-3)])
+# FP8 gaps grow faster with depth than BF16's (measured 1.5e-5, 3.0e-4 and
+# 1.6e-3 for the three nets): where FP32 and FP64 sums round a window's
+# largest activation to different BF16 neighbours, that window's activation
+# scale for the next conv moves, and with it the E4M3 rounding of many operands.
+@pytest.mark.parametrize("prec,tol", [("bf16", 2e-4), ("bf16f", 2e-4), ("fp8", 2e-3)])
 @pytest.mark.parametrize("arch", SHALLOW, ids=lambda a: a.name)
 def test_shallow_resnets_vs_emulation(arch, prec, tol):
     # every low-precision layer kind (stride-1 k7 with the tap-shift operand

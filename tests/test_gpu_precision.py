@@ -25,8 +25,10 @@ def reference():
 
 
 FP8_TAU = pytest.param("fp8", marks=pytest.mark.xfail(strict=False, reason=(
-    "FP8 rank agreement on 16 s of noise: the random-init net's integrated statistic varies by ~0.011 "
-    "across windows while FP8 moves it by up to ~0.006, giving tau ~0.98 (emulated 0.984)")))
+    "FP8 rank agreement on 16 s of noise: the integrated statistic of the random-init net varies by "
+    "~0.011 across windows; rounding the activations alone to E4M3 (weights exact) already gives tau "
+    "0.984 in emulation, and bias correction removes only the weight rounding's systematic shift "
+    "(emulated tau 0.982 with it)")))
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16", "bf16f", FP8_TAU])
@@ -36,6 +38,9 @@ def test_precision_workload(reference, prec):
     xd = torch.from_numpy(reference["x"]).cuda()
     y = P.whiten(xd, P.psd_estimate(xd, FS, 1e21), FS, 1e21)
     net = P.Net(TINY_ARCH, reference["params"], prec)
+    if prec == "fp8":
+        c = np.random.default_rng(99).standard_normal((2, 3072 + 1000 * 15)).astype(np.float32)
+        net.calibrate(torch.from_numpy(c).cuda(), 1000)
     logits = net.score_windows(y, 128)
     integ = P.integrate(logits, 16).cpu().numpy()
     yg, lg = y.cpu().numpy(), logits.cpu().numpy()
