@@ -13,10 +13,16 @@
  * Conventions shared by every entry point
  *  - All data pointers are DEVICE pointers on the current HIP device unless a
  *    parameter says "host".  The caller owns every buffer (inputs, outputs and
- *    workspace); the library owns only af_net objects and its internal
- *    constant tables (FFT twiddles, windows), created on first use per device.
+ *    workspace); the library owns only af_net, af_graph and af_server objects
+ *    and its constant tables (FFT twiddles), which sit in static device arrays
+ *    of the library's code object (nothing is allocated for them).
  *  - Calls are asynchronous on `stream` (a hipStream_t; NULL = default stream).
- *    Only af_net_create synchronises (it uploads the weights).
+ *    The constant tables are computed by a kernel that the first call needing
+ *    them on a device queues on its own stream (calls on other streams wait
+ *    for it on the device, not on the host), or eagerly by af_init.  Calls
+ *    that synchronise say so: af_init, af_net_create(_gn), af_net_calibrate,
+ *    af_net_autotune, af_net_set_layer_tile, af_timeslide_prepare (and
+ *    af_score_timeslides through it) and the streaming server's calls.
  *  - Every argument is validated on the host before anything is launched; an
  *    invalid call returns AF_EINVAL and leaves outputs untouched.  HIP runtime
  *    failures return AF_EHIP.  af_last_error() returns a message for the last
@@ -59,6 +65,12 @@ typedef enum { AF_F32 = 0, AF_BF16 = 1, AF_FP8 = 2, AF_BF16_F32ACT = 3 } af_prec
 
 /* Message describing the last error on this thread ("" if none). */
 const char* af_last_error(void);
+/* Builds the current device's constant tables now and waits for them.
+ * Optional: without it the first call that needs them builds them on its
+ * stream.  Call it once per device before capturing a graph of the PSD,
+ * whitening or SNR entry points (their first call cannot queue the build into
+ * a capture and returns AF_EINVAL instead). */
+af_status af_init(void);
 /* Library version string. */
 const char* af_version(void);
 
@@ -119,7 +131,11 @@ af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t
  * same n_ch, fs and fduration; x, n, ld_x, prescale, n_psd, psd_hop,
  * out_start, n_out, y and ld_y mean what they mean for af_whiten and are
  * checked the same way.  Both return AF_EINVAL before any launch on a bad
- * argument or a buffer that is too small. */
+ * argument or a buffer that is too small; af_whiten_apply also rejects a resp
+ * that no af_whiten_response call of this process filled, or one filled for
+ * another filter length (fduration*fs/2), another channel count or fewer
+ * PSDs (the library records what each af_whiten_response call built, by
+ * buffer address). */
 af_status af_whiten_response(const double* psd, int64_t n_ch, int64_t nperseg, int64_t n_psd, double fs,
                              double fduration, double highpass, void* resp, size_t resp_bytes,
                              af_stream stream);
@@ -309,11 +325,18 @@ void af_graph_destroy(af_graph* graph);
 
 /* ------------------------------------------------------------------------
  * Integration (Sec. II: predictions integrated with a 1 s top-hat filter).
- * Causal right-aligned mean, valid mode:
- *     out[i] = (1/width) sum_{j=i}^{i+width-1} p[j],  i < n - width + 1.
- * n < width writes nothing.
+ * Causal right-aligned mean.  carry == NULL (batch), valid mode:
+ *     out[i] = (1/width) sum_{j=i}^{i+width-1} p[j],  i < n - width + 1;
+ * n < width writes nothing.  carry != NULL (streaming): carry is a device
+ * array of width - 1 floats holding the predictions that precede p (oldest
+ * first); out receives n values, out[i] = the mean of the width values of
+ * carry ++ p that end at p[i], and carry is then replaced by the last
+ * width - 1 values of carry ++ p.  The sums run in the batch order, so a
+ * stream whose carry starts zeroed reproduces the batch values bit for bit
+ * from its width-th output on, however p is chunked.  width - 1 <= 4096
+ * with a carry; width == 1 needs none.
  * ------------------------------------------------------------------------ */
-af_status af_integrate(const float* p, int64_t n, int64_t width, float* out, af_stream stream);
+af_status af_integrate(const float* p, int64_t n, int64_t width, float* carry, float* out, af_stream stream);
 
 /* ------------------------------------------------------------------------
  * Clustering (Sec. II: the integrated series is clustered so that one event

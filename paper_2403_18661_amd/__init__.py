@@ -307,14 +307,22 @@ def score_timeslides(net, y, seg_off, seg_len, shifts, stride=2048, batch=4096, 
     return out
 
 
-def integrate(p, width, out=None, stream=None):
-    """Causal 1 s top-hat mean of logits p [n] -> [n - width + 1] (af_integrate)."""
+def integrate(p, width, carry=None, out=None, stream=None):
+    """Causal 1 s top-hat mean of logits p [n] (af_integrate): -> [n - width + 1]
+    in valid mode, or, with carry (float32 [width - 1] device tensor holding the
+    predictions that precede p, updated in place), -> [n], one per new
+    prediction."""
     _check_dev(p, "p", (torch.float32,))
     n = p.numel()
-    m = max(n - width + 1, 0)
+    if carry is not None:
+        _check_dev(carry, "carry", (torch.float32,))
+        if carry.numel() != width - 1:
+            raise ValueError(f"carry must hold width - 1 = {width - 1} values")
+    m = n if carry is not None else max(n - width + 1, 0)
     if out is None:
         out = torch.empty(m, dtype=torch.float32, device=p.device)
-    check(lib().af_integrate(_ptr(p), n, width, _ptr(out), _stream(stream)))
+    check(lib().af_integrate(_ptr(p), n, width, _ptr(carry) if carry is not None and carry.numel() else None,
+                             _ptr(out), _stream(stream)))
     return out
 
 

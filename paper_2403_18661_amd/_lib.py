@@ -30,6 +30,7 @@ class ServerConfig(ctypes.Structure):
 SIGNATURES = {
     "af_last_error": (ctypes.c_char_p, []),
     "af_version": (ctypes.c_char_p, []),
+    "af_init": (c_int, []),
     "af_psd_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64, c_i64, c_i64, c_i64]),
     "af_psd_estimate": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_i64, c_i64, c_i64, c_i64,
                                 c_i64, c_vp, c_vp, c_sz, c_vp]),
@@ -62,7 +63,7 @@ SIGNATURES = {
     "af_net_profile_end": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "af_score_windows": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp,
                                  c_sz, c_vp]),
-    "af_integrate": (c_int, [c_vp, c_i64, c_i64, c_vp, c_vp]),
+    "af_integrate": (c_int, [c_vp, c_i64, c_i64, c_vp, c_vp, c_vp]),
     "af_timeslide_prepare": (c_int, [c_vp, c_vp, c_vp, c_i64, c_vp, c_i64, c_i64, c_i64, c_vp, c_sz, c_vp]),
     "af_score_timeslides_prepared": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp,
                                              c_vp, c_sz, c_vp]),

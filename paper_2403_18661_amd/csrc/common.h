@@ -41,15 +41,20 @@ void clear_error();
 
 inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
-// ---- per-device constant tables (twiddles, windows) -----------------------
-// Returns a device pointer to exp(-2 pi i t / n) for t < n as interleaved
-// (re, im) doubles; built on the host in FP64 on first use per device.
+// ---- per-device constant tables (twiddles) ---------------------------------
+// Makes sure the current device's tables are built (or being built ahead of
+// later work on s); every entry point that uses a table calls it first.
+// AF_EINVAL while s is capturing a graph and the tables were never built.
+af_status ensure_tables(hipStream_t s);
+// Device pointer to exp(-2 pi i t / n) for t < n as interleaved (re, im)
+// doubles, n a power of two in [2, 8192]; null for other n or before
+// ensure_tables.
 const double* twiddles_f64(int n);
-// Same table rounded to float.
+// exp(-2 pi i t / 512) rounded to float (n = 512 only).
 const float* twiddles_f32(int n);
 // Twiddles of one Stockham pass laid out in the order its butterflies use
 // them: image[(r - 1) ns + k] = exp(-2 pi i r k / n) for 1 <= r < rd, k < ns,
-// as interleaved float (re, im), built in FP64 on first use per device.
+// as interleaved float (re, im); the whitening FFT's (8192, 16, 512) only.
 const float* twiddle_image_f32(int n, int rd, int ns);
 
 // ---- device helpers ---------------------------------------------------------

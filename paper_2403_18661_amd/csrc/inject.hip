@@ -176,8 +176,10 @@ extern "C" af_status af_snr_rescale(float* sig, int64_t n_inj, int64_t n_det, in
     AF_CHECK_ARG(fs > 0.0 && df > 0.0 && f_low >= 0.0 && n_freq >= 2, "need fs > 0, df > 0, f_low >= 0, n_freq >= 2");
     if (n_inj == 0) return AF_OK;
     AF_CHECK_ARG(sig && psd && snr, "sig, psd and snr must be non-null");
+    af_status st = ensure_tables((hipStream_t)stream);
+    if (st != AF_OK) return st;
     const double* tw = twiddles_f64((int)len);
-    AF_CHECK_ARG(tw, "twiddle table allocation failed");
+    AF_CHECK_ARG(tw, "no twiddle table for len = %lld", (long long)len);
     const size_t lds = (size_t)len * sizeof(double2);
     AF_HIP(hipFuncSetAttribute((const void*)snr_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     hipLaunchKernelGGL(snr_kernel, dim3((unsigned)n_inj), dim3(SNR_NT), lds,

@@ -17,8 +17,18 @@ af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n
 int net_window(const af_net* net);
 int net_in_ch(const af_net* net);
 int net_device(const af_net* net);
+
 constexpr int kWhitenBlockOut = 6146;   // outputs per 8192-point block with a 2047-tap filter
 // floats of whitening response per PSD: one (sum, difference) pair per bin of
 // the 8192-point block grid for every detector pair
 inline int64_t whiten_resp_floats(int64_t n_ch) { return ((n_ch + 1) / 2) * 2 * (8192 / 2 + 1); }
+// Bytes of whitening response for n_psd PSDs of n_ch channels.
+size_t resp_bytes_for(int64_t n_ch, int64_t n_psd);
+// Taps per side M of a whitening filter of fduration seconds (AF_EINVAL
+// unless M is a power of two with 2M <= nperseg).
+af_status whiten_taps(double fs, double fduration, int64_t nperseg, int* M_out);
+// Host checks of the data arguments of the whitening entry points.
+af_status whiten_check_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
+                             int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out, const float* y,
+                             int64_t ld_y);
 }  // namespace afm

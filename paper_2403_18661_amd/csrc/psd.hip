@@ -172,9 +172,11 @@ extern "C" af_status af_psd_estimate(const void* x, af_dtype xt, int64_t n_ch, i
     const size_t need = af_psd_workspace_bytes(n_ch, nperseg, noverlap, psd_len, psd_hop, n_psd);
     AF_CHECK_ARG(ws && ws_bytes >= need, "workspace too small: need %zu bytes, got %zu", need, ws_bytes);
     AF_CHECK_ARG(g.n_seg_total < (1LL << 31), "too many segments");
-    const double* tw = twiddles_f64((int)nperseg);
-    if (!tw) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
     hipStream_t s = (hipStream_t)stream;
+    af_status st = ensure_tables(s);
+    if (st != AF_OK) return st;
+    const double* tw = twiddles_f64((int)nperseg);
+    AF_CHECK_ARG(tw, "no twiddle table for nperseg = %lld", (long long)nperseg);
     int logn = 0;
     while ((1LL << logn) < nperseg) ++logn;
     double* pg = (double*)ws;

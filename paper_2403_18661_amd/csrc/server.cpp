@@ -470,7 +470,7 @@ extern "C" af_status af_server_tick(af_server* s, int64_t* n_windows) {
             st.tick_integ_first = st.integ_count;
             st.tick_new_integ = n_int - st.integ_count;
             st.tick_integ_off = n_int_total;
-            af_status r = af_integrate(st.logit + (st.integ_count - st.logit_base), st.logit_count - st.integ_count, W,
+            af_status r = af_integrate(st.logit + (st.integ_count - st.logit_base), st.logit_count - st.integ_count, W, nullptr,
                                        s->d_integ + n_int_total, s->stream);
             if (r != AF_OK) return r;
             n_int_total += st.tick_new_integ;

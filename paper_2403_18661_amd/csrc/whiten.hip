@@ -22,7 +22,10 @@
 // the first inverse pass reads its operands, and the last inverse pass writes
 // its outputs straight to HBM.  Each pass's twiddles and the filter values
 // are loaded a pass ahead of their use.
+#include <atomic>
+#include <mutex>
 #include <type_traits>
+#include <unordered_map>
 
 #include "fft_lds.h"
 #include "internal.h"
@@ -361,10 +364,6 @@ namespace {
 constexpr int FIR_NT = 512;
 constexpr size_t FIR_LDS = (size_t)lds_padded_len(WB_N) * sizeof(cpx<double>);
 
-size_t resp_bytes_for(int64_t n_ch, int64_t n_psd) {
-    return align_up((size_t)n_psd * whiten_resp_floats(n_ch) * sizeof(float), 256);
-}
-
 template <int LOGL>
 hipError_t launch_fir(const double* psd, int64_t n_ch, int64_t n_psd, double fs, double hp, int M,
                       const double* twL, const double* twB, double out_scale, float2* resp, hipStream_t s) {
@@ -378,6 +377,10 @@ hipError_t launch_fir(const double* psd, int64_t n_ch, int64_t n_psd, double fs,
 }
 }  // namespace
 
+size_t afm::resp_bytes_for(int64_t n_ch, int64_t n_psd) {
+    return align_up((size_t)n_psd * whiten_resp_floats(n_ch) * sizeof(float), 256);
+}
+
 extern "C" size_t af_whiten_workspace_bytes(int64_t n_ch, int64_t nperseg, int64_t n_psd) {
     if (n_ch < 1 || n_psd < 1 || (nperseg != 2048 && nperseg != 4096)) return 0;
     return resp_bytes_for(n_ch, n_psd);
@@ -389,9 +392,11 @@ namespace afm {
 // PSD.  Arguments are assumed validated.
 af_status whiten_build_response(const double* psd, int64_t n_ch, int64_t n_psd, int64_t nperseg, double fs,
                                 double highpass, int M, float* resp, hipStream_t s) {
+    af_status st = ensure_tables(s);
+    if (st != AF_OK) return st;
     const double* twL = twiddles_f64((int)nperseg);
     const double* twB = twiddles_f64(WB_N);
-    if (!twL || !twB) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
+    AF_CHECK_ARG(twL && twB, "no twiddle table for nperseg = %lld", (long long)nperseg);
     const double out_scale = sqrt(2.0 / fs) / (double)WB_N;
     float2* r = (float2*)resp;
     hipError_t e = nperseg == 4096 ? launch_fir<12>(psd, n_ch, n_psd, fs, highpass, M, twL, twB, out_scale, r, s)
@@ -404,9 +409,11 @@ af_status whiten_build_response(const double* psd, int64_t n_ch, int64_t n_psd, 
 af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
                        const float* resp, int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out,
                        float* y, int64_t ld_y, hipStream_t s) {
+    af_status st = ensure_tables(s);
+    if (st != AF_OK) return st;
     const float* tw512 = twiddles_f32(512);
     const float* img3 = twiddle_image_f32(WB_N, 16, 512);
-    if (!tw512 || !img3) { set_error("twiddle table allocation failed"); return AF_ENOMEM; }
+    if (!tw512 || !img3) { set_error("whitening twiddle tables missing"); return AF_EHIP; }
     const int V = WB_N - 2 * (M - 1);
     if (n_psd <= 1) psd_hop = n_out;
     const int64_t bph = (psd_hop + V - 1) / V;
@@ -429,7 +436,7 @@ af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int6
 }
 }  // namespace afm
 
-namespace {
+namespace afm {
 // M = fduration*fs/2 taps per side: a power of two with 2M <= nperseg whose
 // filter leaves valid outputs in an 8192-point block.
 af_status whiten_taps(double fs, double fduration, int64_t nperseg, int* M_out) {
@@ -459,6 +466,19 @@ af_status whiten_check_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n
                      "psd_hop must be >= 1 and every PSD hop must start inside the output");
     return AF_OK;
 }
+}  // namespace afm
+
+namespace {
+// What each af_whiten_response call built, by buffer address, so that
+// af_whiten_apply can reject a buffer built for another filter length,
+// channel count or fewer PSDs.
+struct RespInfo {
+    int M;
+    int64_t n_ch, n_psd;
+};
+std::mutex g_resp_mu;
+std::unordered_map<const void*, RespInfo> g_resp;
+
 }  // namespace
 
 extern "C" af_status af_whiten_response(const double* psd, int64_t n_ch, int64_t nperseg, int64_t n_psd, double fs,
@@ -474,7 +494,12 @@ extern "C" af_status af_whiten_response(const double* psd, int64_t n_ch, int64_t
     if (st != AF_OK) return st;
     const size_t need = resp_bytes_for(n_ch, n_psd);
     AF_CHECK_ARG(resp_bytes >= need, "response buffer too small: need %zu bytes, got %zu", need, resp_bytes);
-    return whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, (float*)resp, (hipStream_t)stream);
+    st = whiten_build_response(psd, n_ch, n_psd, nperseg, fs, highpass, M, (float*)resp, (hipStream_t)stream);
+    if (st == AF_OK) {
+        std::lock_guard<std::mutex> lk(g_resp_mu);
+        g_resp[resp] = RespInfo{M, n_ch, n_psd};
+    }
+    return st;
 }
 
 extern "C" af_status af_whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double fs,
@@ -491,6 +516,17 @@ extern "C" af_status af_whiten_apply(const void* x, af_dtype xt, int64_t n_ch, i
     if (st != AF_OK) return st;
     const size_t need = resp_bytes_for(n_ch, n_psd);
     AF_CHECK_ARG(resp_bytes >= need, "response buffer too small: need %zu bytes, got %zu", need, resp_bytes);
+    RespInfo info{0, 0, 0};
+    {
+        std::lock_guard<std::mutex> lk(g_resp_mu);
+        auto it = g_resp.find(resp);
+        AF_CHECK_ARG(it != g_resp.end(), "resp was not filled by af_whiten_response");
+        info = it->second;
+    }
+    AF_CHECK_ARG(info.M == M, "resp holds filters of %d taps per side; fduration*fs/2 = %d", info.M, M);
+    AF_CHECK_ARG(info.n_ch == n_ch && info.n_psd >= n_psd,
+                 "resp holds %lld PSDs of %lld channels; asked for %lld of %lld", (long long)info.n_psd,
+                 (long long)info.n_ch, (long long)n_psd, (long long)n_ch);
     return whiten_apply(x, xt, n_ch, n, ld_x, prescale, (const float*)resp, n_psd, psd_hop, M, out_start, n_out, y,
                         ld_y, (hipStream_t)stream);
 }
@@ -517,3 +553,4 @@ extern "C" af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t
     if (st != AF_OK) return st;
     return whiten_apply(x, xt, n_ch, n, ld_x, prescale, resp, n_psd, psd_hop, M, out_start, n_out, y, ld_y, s);
 }
+

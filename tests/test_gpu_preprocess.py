@@ -163,3 +163,81 @@ def test_whiten_response_apply_split():
         P.whiten_apply(xd, small, n_psd, FS, PRESCALE, hop, out_start=out_start, n_out=n_out)
     with pytest.raises(P.AframeError):
         P.whiten_response(psd, FS, out=small)
+
+
+def test_integrate_carry_streams_equal_the_batch():
+    # chunks of every size (shorter than the carry, single samples, long runs)
+    # through one carry give the batch values bit for bit from the width-th
+    # output on
+    P = need_gpu()
+    import torch
+    banner("integrate with carry")
+    for width in (16, 4, 2048):
+        n = 5000
+        p = dev(np.random.default_rng(width).standard_normal(n).astype(np.float32))
+        ref = P.integrate(p, width).cpu().numpy()
+        carry = torch.zeros(width - 1, dtype=torch.float32, device="cuda")
+        outs, i = [], 0
+        for size in (5, 1, 37, 300, 1, 2100, 0, 2556):
+            outs.append(P.integrate(p[i:i + size], width, carry=carry).cpu().numpy())
+            i += size
+        assert i == n
+        got = np.concatenate(outs)
+        assert got.shape == (n,)
+        np.testing.assert_array_equal(got[width - 1:], ref)
+        np.testing.assert_array_equal(carry.cpu().numpy(), p[n - width + 1:].cpu().numpy())
+    one = dev(np.arange(7, dtype=np.float32))
+    np.testing.assert_array_equal(P.integrate(one, 1, carry=torch.zeros(0, device="cuda")).cpu().numpy(),
+                                  np.arange(7, dtype=np.float32))
+
+
+def test_whiten_apply_checks_the_response_it_is_given():
+    # a response built for another filter length, fewer PSDs or another
+    # channel count, or one no af_whiten_response call filled, is rejected
+    P = need_gpu()
+    import torch
+    fs = int(FS)
+    xd = dev(coloured_noise(fs * 40, seed=78))
+    psd = P.psd_estimate(xd, FS, PRESCALE)
+    resp = P.whiten_response(psd, FS, fduration=1.0)
+    ok = P.whiten_apply(xd, resp, 1, FS, PRESCALE, fduration=1.0)
+    assert ok.shape[1] == xd.shape[1] - fs
+    with pytest.raises(P.AframeError, match="taps"):
+        P.whiten_apply(xd, resp, 1, FS, PRESCALE, fduration=0.5)
+    with pytest.raises(P.AframeError, match="PSDs"):
+        P.whiten_apply(xd, resp, 2, FS, PRESCALE, psd_hop=8 * fs, fduration=1.0)
+    with pytest.raises(P.AframeError, match="af_whiten_response"):
+        P.whiten_apply(xd, torch.zeros_like(resp), 1, FS, PRESCALE, fduration=1.0)
+
+
+def test_psd_and_whitening_captured_after_init_replay_equal():
+    # af_init builds the constant tables up front, so the PSD and whitening
+    # calls can be captured in a graph; every replay equals the direct calls
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.timeslides import Graph
+    banner("psd + whiten graph capture")
+    P.check(P.lib().af_init())
+    fs = int(FS)
+    xd = dev(coloured_noise(fs * 24, seed=79))
+    ws_p = torch.empty(P.lib().af_psd_workspace_bytes(2, 4096, 2048, xd.shape[1], 0, 1), dtype=torch.uint8,
+                       device="cuda")
+    ws_w = torch.empty(P.lib().af_whiten_workspace_bytes(2, 4096, 1), dtype=torch.uint8, device="cuda")
+    psd_ref = P.psd_estimate(xd, FS, PRESCALE, ws=ws_p)
+    y_ref = P.whiten(xd, psd_ref, FS, PRESCALE, ws=ws_w)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    psd = torch.empty_like(psd_ref)
+    y = torch.empty_like(y_ref)
+    g = Graph(s)
+    with g:   # every buffer exists beforehand: nothing is allocated during the capture
+        P.psd_estimate(xd, FS, PRESCALE, out=psd, ws=ws_p, stream=s)
+        P.whiten(xd, psd, FS, PRESCALE, out=y, ws=ws_w, stream=s)
+    for rep in range(3):
+        y.fill_(float("nan"))
+        torch.cuda.synchronize()
+        g.launch()
+        s.synchronize()
+        assert torch.equal(psd, psd_ref) and torch.equal(y, y_ref)
+        _ = (xd * 2).sum().item()        # unrelated eager work between replays
+    g.close()

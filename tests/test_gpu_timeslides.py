@@ -77,3 +77,34 @@ def test_prepared_graph_replays_match_direct_call():
         plan.stream.synchronize()
         np.testing.assert_array_equal(plan.logits[:plan.n_windows].cpu().numpy(), direct)
         _ = (y * 2).sum().item()          # unrelated eager work between replays
+
+
+def test_graph_replays_after_a_tile_switch():
+    # a graph captured on the layer path keeps the weight image and tile it
+    # captured; switching a layer's tile afterwards leaves its replays equal
+    # to the direct call
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.timeslides import TimeslidePlan
+    banner("graph replay after set_tile")
+    params = make_params(TINY_ARCH, seed=17)
+    y = dev(np.random.default_rng(18).standard_normal((2, 20000)).astype(np.float32))
+    net = P.Net(TINY_ARCH, params, "f32")
+    seg_off, seg_len, shifts = [0, 9000], [9000, 11000], [2048 * k for k in range(1, 4)]
+    direct = P.score_timeslides(net, y, seg_off, seg_len, shifts, stride=1024).cpu().numpy()
+    plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=1024, graph=True)
+    tiles = net.tiles()
+    switched = 0
+    for layer, (_, _, n_cand, chosen) in enumerate(tiles, start=1):
+        if n_cand > 1:
+            net.set_tile(layer, (chosen + 1) % n_cand)
+            switched += 1
+    assert switched > 0
+    for rep in range(2):
+        plan.logits.fill_(float("nan"))
+        torch.cuda.synchronize()
+        plan.run()
+        plan.stream.synchronize()
+        np.testing.assert_array_equal(plan.logits[:plan.n_windows].cpu().numpy(), direct)
+    np.testing.assert_array_equal(P.score_timeslides(net, y, seg_off, seg_len, shifts, stride=1024).cpu().numpy(),
+                                  direct)
