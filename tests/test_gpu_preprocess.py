@@ -204,7 +204,11 @@ def test_whiten_apply_checks_the_response_it_is_given():
     assert ok.shape[1] == xd.shape[1] - fs
     with pytest.raises(P.AframeError, match="taps"):
         P.whiten_apply(xd, resp, 1, FS, PRESCALE, fduration=0.5)
+    roomy = torch.empty(2 * resp.numel(), dtype=torch.uint8, device="cuda")   # room for two PSDs, filled with one
+    P.whiten_response(psd, FS, out=roomy)
     with pytest.raises(P.AframeError, match="PSDs"):
+        P.whiten_apply(xd, roomy, 2, FS, PRESCALE, psd_hop=8 * fs, fduration=1.0)
+    with pytest.raises(P.AframeError, match="too small"):
         P.whiten_apply(xd, resp, 2, FS, PRESCALE, psd_hop=8 * fs, fduration=1.0)
     with pytest.raises(P.AframeError, match="af_whiten_response"):
         P.whiten_apply(xd, torch.zeros_like(resp), 1, FS, PRESCALE, fduration=1.0)
