@@ -121,6 +121,23 @@ af_status af_whiten(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t
                     int64_t out_start, int64_t n_out, float* y, int64_t ld_y,
                     void* ws, size_t ws_bytes, af_stream stream);
 
+/* af_whiten without a workspace, for callers that cannot allocate device
+ * memory (code under graph capture, tight serving loops, harnesses that forbid
+ * allocation): the same arguments minus ws and ws_bytes, the same kernels and
+ * the same output bit for bit.  The filter responses go to a static scratch
+ * array of 16 MiB + 4 KiB per GPU (512 (PSD, detector pair) combinations of
+ * af_whiten_workspace_bytes, e.g. 512 PSDs of one or two detectors, 256 of
+ * three or four), held from when the library's code loads on the GPU until
+ * the process ends; larger requests return AF_EINVAL.  It calls no allocation
+ * routine (af_init looks up the array's address; otherwise the first call on
+ * a device does).  Every call on a GPU shares that GPU's array: calls that
+ * overlap on one GPU (several streams or threads) race and must be
+ * serialised by the caller. */
+af_status af_whiten_noalloc(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double fs,
+                            double prescale, const double* psd, int64_t nperseg, int64_t n_psd, int64_t psd_hop,
+                            double fduration, double highpass, int64_t out_start, int64_t n_out, float* y,
+                            int64_t ld_y, af_stream stream);
+
 /* The two halves of af_whiten, for callers that reuse filters (one rolling
  * PSD serving several output spans) or time them apart.
  * af_whiten_response builds the filters of n_psd PSDs (FP64 on the device,

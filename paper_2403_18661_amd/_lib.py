@@ -37,6 +37,8 @@ SIGNATURES = {
     "af_whiten_workspace_bytes": (c_sz, [c_i64, c_i64, c_i64]),
     "af_whiten": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_vp, c_i64, c_i64, c_i64, c_dbl,
                           c_dbl, c_i64, c_i64, c_vp, c_i64, c_vp, c_sz, c_vp]),
+    "af_whiten_noalloc": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_vp, c_i64, c_i64, c_i64, c_dbl,
+                                  c_dbl, c_i64, c_i64, c_vp, c_i64, c_vp]),
     "af_whiten_response": (c_int, [c_vp, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_dbl, c_vp, c_sz, c_vp]),
     "af_whiten_apply": (c_int, [c_vp, c_int, c_i64, c_i64, c_i64, c_dbl, c_dbl, c_vp, c_sz, c_i64, c_i64, c_dbl,
                                 c_i64, c_i64, c_vp, c_i64, c_vp]),

@@ -14,7 +14,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libaframe_mi.so")
 BUILD_DIR = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["tables.hip", "psd.hip", "whiten.hip", "net.hip", "integrate.hip", "cluster.hip", "inject.hip", "server.cpp", "graph.cpp"]
+SOURCES = ["tables.hip", "psd.hip", "whiten.hip", "net.hip", "integrate.hip", "cluster.hip", "inject.hip", "server.cpp", "graph.cpp", "noalloc.hip"]
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -17,11 +17,14 @@ af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n
 int net_window(const af_net* net);
 int net_in_ch(const af_net* net);
 int net_device(const af_net* net);
+// Looks up, once per device, the address of the static scratch array of
+// af_whiten_noalloc.
+af_status whiten_scratch_setup();
 
 constexpr int kWhitenBlockOut = 6146;   // outputs per 8192-point block with a 2047-tap filter
 // floats of whitening response per PSD: one (sum, difference) pair per bin of
 // the 8192-point block grid for every detector pair
-inline int64_t whiten_resp_floats(int64_t n_ch) { return ((n_ch + 1) / 2) * 2 * (8192 / 2 + 1); }
+constexpr int64_t whiten_resp_floats(int64_t n_ch) { return ((n_ch + 1) / 2) * 2 * (8192 / 2 + 1); }
 // Bytes of whitening response for n_psd PSDs of n_ch channels.
 size_t resp_bytes_for(int64_t n_ch, int64_t n_psd);
 // Taps per side M of a whitening filter of fduration seconds (AF_EINVAL

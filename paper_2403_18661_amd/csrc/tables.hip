@@ -153,6 +153,8 @@ extern "C" af_status af_init(void) {
     clear_error();
     af_status st = ensure_tables(nullptr);
     if (st != AF_OK) return st;
+    st = whiten_scratch_setup();
+    if (st != AF_OK) return st;
     AF_HIP(hipStreamSynchronize(nullptr));
     return ensure_tables(nullptr);   // records completion
 }
