@@ -126,6 +126,8 @@ def timeslide_leg(args, P, log):
     log(f"timeslide: {len(seg_len)} segments whitened ({off / fs / 3600:.2f} h of output) in "
         f"{time.perf_counter() - t0:.1f} s")
     shifts = [k * fs for k in range(1, 101)]
+    changed = net.autotune(batch=8192)
+    log(f"timeslide: autotune changed {changed}; rows per step {net.fused_tile()[0]}")
     plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=fs, graph=True)
     for _ in range(args.warmup):
         plan.run()
@@ -143,6 +145,7 @@ def timeslide_leg(args, P, log):
     res = {"windows_per_step": plan.n_windows, "segments": len(seg_len), "slides": len(shifts),
            "value": plan.n_windows * args.steps / dt, "unit": "windows/s", "ms_per_step": 1e3 * dt / args.steps,
            "dtype": "bf16", "kernel": "fused_tiny_bf16_kernel (one persistent launch, hipGraph replay)",
+           "rows_per_step": net.fused_tile()[0],
            "achieved_tflops": flop / (ms * 1e-3) * 1e-12, "peak_tflops": PEAK_TFLOPS["bf16"],
            "frac": flop / (ms * 1e-3) * 1e-12 / PEAK_TFLOPS["bf16"], "kernel_ms": ms}
     log(f"timeslide: {res['value']:.0f} windows/s, {res['achieved_tflops']:.1f} TFLOP/s")
@@ -366,6 +369,8 @@ def main():
     ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--no-inject", action="store_true")
     ap.add_argument("--no-gn", action="store_true")
+    ap.add_argument("--timeslide-only", action="store_true",
+                    help="run only the timeslide leg (e.g. to profile its kernel) and print its JSON")
     ap.add_argument("--streams", default="1,16,64")
     ap.add_argument("--stream-seconds", type=float, default=15.0)
     args = ap.parse_args()
@@ -384,6 +389,9 @@ def main():
     from synth.workloads import hour_strain, PSD_LEN
 
     arch = RESNET_ARCH
+    if args.timeslide_only:
+        print(json.dumps({"timeslide": timeslide_leg(args, P, log)}), flush=True)
+        return
     if args.calib_copy_mb > 0:
         src = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)

@@ -236,11 +236,17 @@ int64_t af_net_macs(const af_net* net);
 
 /* Whole-network path.  For the 16-channel two-block net (stem 2->16 k7 s1,
  * one stage of two BasicBlocks) in BF16, scoring runs as one persistent kernel
- * that keeps every activation in LDS (on by default).  af_net_fused reports
- * whether it is active; af_net_set_fused(net, 0) selects the layer-by-layer
- * kernels instead (AF_EINVAL if enabling it on a net without the path). */
+ * (one wavefront per window, every activation in LDS; on by default).
+ * af_net_fused reports whether it is active; af_net_set_fused(net, 0) selects
+ * the layer-by-layer kernels instead (AF_EINVAL if enabling it on a net
+ * without the path).  The kernel walks a window in steps of `rows` time rows;
+ * af_net_fused_tile reports the candidates' count and the one in use, which
+ * af_net_autotune picks by timing and af_net_set_fused_tile sets (logits are
+ * the same bit for bit under every candidate). */
 int af_net_fused(const af_net* net);
 af_status af_net_set_fused(af_net* net, int enable);
+af_status af_net_fused_tile(const af_net* net, int32_t* rows, int32_t* n_candidates, int32_t* chosen);
+af_status af_net_set_fused_tile(af_net* net, int32_t chosen);
 
 /* Number of timed layers: stem, each conv in execution order, GAP+FC head;
  * GroupNorm nets (af_net_create_gn) have one more, after the head, that

@@ -196,6 +196,15 @@ class Net:
     def fused(self, enable):
         check(lib().af_net_set_fused(self._h, int(bool(enable))))
 
+    def fused_tile(self):
+        """(rows per step, candidates, chosen) of the whole-network kernel."""
+        v = [ctypes.c_int32() for _ in range(3)]
+        check(lib().af_net_fused_tile(self._h, *[ctypes.byref(x) for x in v]))
+        return tuple(x.value for x in v)
+
+    def set_fused_tile(self, chosen):
+        check(lib().af_net_set_fused_tile(self._h, chosen))
+
     @property
     def n_layers(self):
         return lib().af_net_n_layers(self._h)

@@ -61,6 +61,9 @@ SIGNATURES = {
     "af_net_layer_tile": (c_int, [c_vp, c_i64, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                   ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32)]),
     "af_net_set_fused": (c_int, [c_vp, c_int]),
+    "af_net_fused_tile": (c_int, [c_vp, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
+                                  ctypes.POINTER(ctypes.c_int32)]),
+    "af_net_set_fused_tile": (c_int, [c_vp, ctypes.c_int32]),
     "af_net_profile_begin": (c_int, [c_vp]),
     "af_net_profile_end": (c_int, [c_vp, c_i64, c_vp, c_vp, c_vp]),
     "af_score_windows": (c_int, [c_vp, c_vp, c_i64, c_i64, c_i64, c_i64, c_i64, c_vp, c_i64, c_vp, c_vp,

@@ -1,185 +1,252 @@
-// Whole-network kernel for the 16-channel, two-block ResNet (stem k7 s1,
-// two BasicBlocks of 16 channels, GAP, FC) in BF16, persistent over windows.
+// Whole-network kernel for the 16-channel, two-block ResNet (stem k7 s1, two
+// BasicBlocks of 16 channels, GAP, FC) in BF16: one wavefront per window,
+// persistent over windows.
 //
-// Each workgroup walks windows g = blockIdx.x, blockIdx.x + gridDim.x, ...
-// (every wave leaves the loop when g passes n_windows).  A window is processed
-// in time tiles of T = 232 outputs.  The tile's 256 rows cover times
-// t0 - 12 ... t0 + T + 11: the four k7 convs each shrink the valid range by 3
-// rows per side, so the last layer is valid on [t0, t0 + T).  Rows outside the
-// window are forced to zero after every layer, which is the per-layer zero
-// padding of the unfused network.  All activations stay in LDS (BF16); the
-// four conv weight matrices stay in registers for the workgroup's lifetime.
+// A wavefront walks its window in steps of T time rows.  In step k the stem
+// produces rows [kT, kT + T) and conv layer l (l = 1..4) the rows
+// [kT - 3l, kT + T - 3l).  A k7 conv reads 3 rows beyond its output on each
+// side; the layer before produced them in this step or in the previous one,
+// whose last 6 rows every buffer carries to its front, so no row is computed
+// twice.  Rows outside the window are forced to zero (the per-layer zero
+// padding of the unfused network); a 16-row tile wholly outside is not
+// computed.  Activations stay in the wavefront's LDS (BF16), weights in
+// registers.  With one wavefront per workgroup, ordering its own LDS accesses
+// between layers needs no barrier, only a wait for its LDS operations
+// (wave_lds_sync); the next step's input loads stay in flight meanwhile.
 //
-// Each conv is computed transposed on 16x16x32 BF16 MFMA tiles:
-// D[channel][time] = W[channel][k] * X[k][time], k = tap * 16 + channel_in
-// (tap 7 is a zero pad that brings K = 112 to 128), so that a lane ends up with
-// four consecutive output channels of one time row and stores them as 8 bytes.
+// Every layer runs on the matrix cores, transposed (D[channel][time] =
+// W[channel][k] X[k][time]) so that a lane ends with four consecutive
+// channels of one time row:
+//  - stem: FP32 16x16x4 MFMAs over k = input channel x 8 + tap (the eighth
+//    tap has weight 0), FP32 weights and input;
+//  - convs: BF16 16x16x32 MFMAs over k = tap x 16 + channel.  The eighth tap
+//    pads K from 112 to 128; in the second conv of a block it carries the
+//    residual (identity weights times the block input's row), which is then
+//    summed in FP32 with the products;
+//  - the bias is the accumulator's initial value.
+// Outputs are rounded to BF16 (hardware round-to-nearest-even) and then
+// passed through ReLU as packed 16-bit integers (a BF16 value is negative iff
+// its bit pattern is, and rounding commutes with max(., 0)); the second
+// block's output goes to the global average, then FC.
 #pragma once
 #include "net_kernels.h"
 
 namespace afm {
 
 struct FusedTinyArgs {
-    StemArgs st;               // addressing + stem weights (FP32), window length
-    const uint16_t* wconv;     // [4][16][128] BF16, layer-major, k = tap*16 + c
-    const float* bconv;        // [4][16]
-    const float* fc_w;         // [16]
-    float fc_b;
+    StemArgs st;               // window addressing and window length
+    const float* wstem;        // [16][16]: output channel, k = input channel * 8 + tap (tap 7: 0)
+    const uint16_t* wconv;     // [4][16][128] BF16, k = tap * 16 + channel; tap 7 as described above
+    const float* bias;         // [5][16]: stem, then the four convs
+    const float* fc;           // [16] weights, then the bias
     float* logits;
     int64_t n_windows;
 };
 
+// Waits for this wavefront's outstanding LDS operations and keeps the
+// compiler from moving memory accesses across the point; global loads in
+// flight are not waited for.
+__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// BF16 pair: round to nearest even, then ReLU on the bit patterns (one packed
+// signed 16-bit max); zero where `keep` is false.
+typedef short short2v __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t relu_bf16x2(float lo, float hi) {
+    const short2v v = __builtin_bit_cast(short2v, pack_bf16x2(lo, hi));
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, short2v{0, 0}));
+}
+// A tile's four outputs (channels 4g .. 4g + 3 of one time row) as stored:
+// rows whose time lies outside [0, L) become zero.  `edge` (the same on every
+// lane) says whether the tile reaches outside; only then is the row tested.
+__device__ __forceinline__ uint2 finish_tile(const f4v& acc, bool edge, int t, int L) {
+    uint2 p = make_uint2(relu_bf16x2(acc[0], acc[1]), relu_bf16x2(acc[2], acc[3]));
+    if (edge && (t < 0 || t >= L)) p = make_uint2(0u, 0u);
+    return p;
+}
+
 namespace fused_tiny {
 constexpr int C = 16;
-constexpr int R = 256;          // rows per tile (one per thread for the stem)
-constexpr int HALO = 12;        // 4 convs x 3
-constexpr int T = R - 2 * HALO; // valid outputs per tile
-constexpr int XR = R + 6;       // input samples per tile and channel
-constexpr int PITCH = 24;       // BF16 elements per activation row (48 B: conflict-free 16 B reads)
-constexpr int GUARD = 3;        // rows before row 0
-constexpr int ROWS = R + 8;     // GUARD + R + 5 (tap 7 reads row q + 7)
-constexpr int BUF = ROWS * PITCH;
+constexpr int TAIL = 6;         // rows carried from step to step
+template <int T, int PITCH>
+struct Geo {
+    static constexpr int ROWS = T + TAIL;      // rows per activation buffer
+    static constexpr int BUF = ROWS * PITCH;   // elements per buffer
+    static constexpr int XN = T + TAIL;        // input samples per channel
+    static constexpr int LDS = 4 * BUF * 2 + 2 * XN * 4 + 5 * C * 4;
+};
 }  // namespace fused_tiny
 
-__global__ void __launch_bounds__(256) fused_tiny_bf16_kernel(FusedTinyArgs a) {
+// T: time rows per step; PITCH: BF16 elements per stored activation row (16
+// channels and padding, which sets the LDS bank pattern of the operand reads)
+template <int T, int PITCH>
+__global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a) {
     using namespace fused_tiny;
-    __shared__ __attribute__((aligned(16))) uint16_t act[3 * BUF];
-    __shared__ float xs[2 * XR];
-    __shared__ float gpart[4 * C];
-    const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
-    const int g = lane >> 4, r16 = lane & 15;
+    using G = Geo<T, PITCH>;
+    static_assert(T % 16 == 0 && (T <= 64 || T % 64 == 0), "steps of whole 16-row tiles");
+    constexpr int NT = T / 16;                  // row tiles per layer and step
+    __shared__ __attribute__((aligned(16))) uint16_t act[4 * G::BUF];   // stem, conv 1, conv 2, conv 3 outputs
+    __shared__ float xs[2 * G::XN];
+    __shared__ __attribute__((aligned(16))) float sbias[5 * C];   // read per layer and step: fewer live registers
+    const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
     const int L = a.st.window;
+    const int64_t ld = a.st.ld_y;
 
-    // zero the guard rows once; tiles only ever write rows GUARD .. GUARD + R - 1
-    for (int e = tid; e < 3 * 8 * PITCH; e += 256) {
-        const int b = e / (8 * PITCH), rr = (e / PITCH) % 8, c = e % PITCH;
-        const int row = rr < GUARD ? rr : R + rr;   // rows 0..2 and R+3..R+7
-        act[b * BUF + row * PITCH + c] = 0;
-    }
-    // conv weights (A operand) for all four layers and bias
+    // weights and biases for the kernel's lifetime
+    float ws[4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) ws[s] = a.wstem[r16 * 16 + 4 * s + g];
     bf16x8 wa[4][4];
 #pragma unroll
     for (int l = 0; l < 4; ++l)
 #pragma unroll
         for (int s = 0; s < 4; ++s)
             wa[l][s] = *(const bf16x8*)(a.wconv + ((size_t)l * C + r16) * 128 + 32 * s + 8 * g);
-    float bias[4][4];
+    for (int e = lane; e < 5 * C; e += 64) sbias[e] = a.bias[e];
+    auto bias = [&](int l) { return *(const f4v*)(sbias + l * C + 4 * g); };
+    float fcw[4];
 #pragma unroll
-    for (int l = 0; l < 4; ++l)
-#pragma unroll
-        for (int r = 0; r < 4; ++r) bias[l][r] = a.bconv[l * C + 4 * g + r];
-    __syncthreads();
+    for (int r = 0; r < 4; ++r) fcw[r] = a.fc[4 * g + r];
+    const float fcb = a.fc[C];
 
-    uint16_t* bufA = act;
-    uint16_t* bufB = act + BUF;
-    uint16_t* bufC = act + 2 * BUF;
+    auto buf = [&](int b) { return act + b * G::BUF; };
+    const int nsteps = (L + 12 + T - 1) / T;
 
     for (int64_t win = blockIdx.x; win < a.n_windows; win += gridDim.x) {
         const WinAddr wad = window_addr(a.st, win);
-        float gsum[4] = {0.f, 0.f, 0.f, 0.f};
-        for (int t0 = 0; t0 < L; t0 += T) {
-            // stage the input samples t0 - 15 ... t0 + T + 14 of both detectors
-            for (int e = tid; e < 2 * XR; e += 256) {
-                const int ci = e / XR, u = e % XR;
-                const int t = t0 - HALO - 3 + u;
-                xs[e] = (t >= 0 && t < L) ? a.st.y[ci * a.st.ld_y + window_sample(wad, ci, t)] : 0.f;
-            }
-            __syncthreads();
-            // stem: row q = tid, time t0 - 12 + q, all 16 channels (FP32, stored BF16)
-            {
-                const int q = tid, t = t0 - HALO + q;
-                float xin[2][7];
+        auto sample = [&](int c, int t) -> float {
+            return (t >= 0 && t < L) ? a.st.y[c * ld + window_sample(wad, c, t)] : 0.f;
+        };
+        // window start: the carried rows lie before the window (zero); the
+        // input's carried samples are those of times -3 .. 2
+        for (int e = lane; e < 4 * TAIL * 3; e += 64) {
+            const int b = e / (TAIL * 3), u = e % (TAIL * 3);
+            *(uint4*)(buf(b) + (u / 3) * PITCH + (u % 3) * 8) = make_uint4(0u, 0u, 0u, 0u);
+        }
+        if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = sample(lane / TAIL, lane % TAIL - 3);
+        // samples of times s0 + 3 .. s0 + T + 2 of step 0 (T / 64 per lane and channel)
+        constexpr int PER = T >= 64 ? T / 64 : 1;
+        float nx[2][PER];
 #pragma unroll
-                for (int ci = 0; ci < 2; ++ci)
+        for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int j = 0; j < 7; ++j) xin[ci][j] = xs[ci * XR + q + j];
-                const bool inside = t >= 0 && t < L;
-                uint32_t packed[C / 2];
-#pragma unroll
-                for (int c = 0; c < C; c += 2) {
-                    float v[2];
-#pragma unroll
-                    for (int h = 0; h < 2; ++h) {
-                        float sacc = a.st.b[c + h];
-#pragma unroll
-                        for (int ci = 0; ci < 2; ++ci)
-#pragma unroll
-                            for (int j = 0; j < 7; ++j) sacc = fmaf(a.st.w[((c + h) * 2 + ci) * 7 + j], xin[ci][j], sacc);
-                        v[h] = inside ? fmaxf(sacc, 0.f) : 0.f;
-                    }
-                    packed[c / 2] = pack_bf16x2(v[0], v[1]);
-                }
-                uint4* dst = (uint4*)(bufA + (q + GUARD) * PITCH);
-                dst[0] = make_uint4(packed[0], packed[1], packed[2], packed[3]);
-                dst[1] = make_uint4(packed[4], packed[5], packed[6], packed[7]);
-            }
-            __syncthreads();
+            for (int p = 0; p < PER; ++p) nx[c][p] = (lane + 64 * p < T) ? sample(c, 3 + lane + 64 * p) : 0.f;
+        f4v gs = {0.f, 0.f, 0.f, 0.f};
 
-            // one conv layer: in -> out (or GAP when out == null); residual optional
-            auto layer = [&](int l, const uint16_t* in, uint16_t* out, const uint16_t* res) {
+        for (int k = 0; k < nsteps; ++k) {
+            const int s0 = k * T;
 #pragma unroll
-                for (int m = 0; m < 4; ++m) {
-                    const int q0 = (wave * 4 + m) * 16;     // first row of this 16-row tile
-                    f4v acc = {0.f, 0.f, 0.f, 0.f};
+            for (int c = 0; c < 2; ++c)
 #pragma unroll
-                    for (int s = 0; s < 4; ++s) {
-                        const int k0 = 32 * s + 8 * g;
-                        const int j = k0 >> 4, c0 = k0 & 15;
-                        const bf16x8 xb = *(const bf16x8*)(in + (q0 + r16 + j) * PITCH + c0);
-                        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[l][s], xb, acc, 0, 0, 0);
-                    }
-                    const int q = q0 + r16, t = t0 - HALO + q;
-                    const bool inside = t >= 0 && t < L;
-                    float v[4];
-                    uint2 rres = make_uint2(0u, 0u);
-                    if (res) rres = *(const uint2*)(res + (q + GUARD) * PITCH + 4 * g);
+                for (int p = 0; p < PER; ++p)
+                    if (lane + 64 * p < T) xs[c * G::XN + TAIL + lane + 64 * p] = nx[c][p];
+            // the next step's samples are loaded now and stored a step later
+            if (k + 1 < nsteps) {
 #pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        float x = acc[r] + bias[l][r];
-                        if (res) {
-                            const uint32_t w2 = r < 2 ? rres.x : rres.y;
-                            x += __uint_as_float((r & 1) ? (w2 & 0xFFFF0000u) : (w2 << 16));
-                        }
-                        x = inside ? fmaxf(x, 0.f) : 0.f;
-                        v[r] = bf16_bits_to_f32(f32_to_bf16_bits(x));
-                    }
+                for (int c = 0; c < 2; ++c)
+#pragma unroll
+                    for (int p = 0; p < PER; ++p)
+                        nx[c][p] = (lane + 64 * p < T) ? sample(c, s0 + T + 3 + lane + 64 * p) : 0.f;
+            }
+            wave_lds_sync();
+
+            // ---- stem: rows s0 .. s0 + T - 1 into buffer 0 (rows TAIL ..)
+            {
+                const int j0 = 4 * 0 + g, j1 = 4 + g;   // taps of the even / odd k-steps
+                const float* xb[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = (s & 1) ? j1 : j0;
+                    xb[s] = xs + (s >> 1) * G::XN + r16 + (j == 7 ? 6 : j);   // tap 7: any sample, weight 0
+                }
+                // the tiles' accumulation chains interleaved; tiles past the
+                // window are computed too (their rows are then zeroed)
+                f4v acc[NT];
+#pragma unroll
+                for (int m = 0; m < NT; ++m) acc[m] = bias(0);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    float xv[NT];
+#pragma unroll
+                    for (int m = 0; m < NT; ++m) xv[m] = xb[s][16 * m];
+#pragma unroll
+                    for (int m = 0; m < NT; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ws[s], xv[m], acc[m], 0, 0, 0);
+                }
+#pragma unroll
+                for (int m = 0; m < NT; ++m) {
+                    const int t0 = s0 + 16 * m;
+                    *(uint2*)(buf(0) + (TAIL + 16 * m + r16) * PITCH + 4 * g) =
+                        finish_tile(acc[m], t0 + 15 >= L, t0 + r16, L);
+                }
+            }
+            wave_lds_sync();
+
+            // ---- conv layer l: buffer l -> buffer l + 1 (or the average)
+            auto conv = [&](const int l, const uint16_t* in, const uint16_t* res, uint16_t* out) {
+                const uint16_t* bsrc[4];
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    const int j = 2 * s + (g >> 1), c0 = 8 * (g & 1);
+                    bsrc[s] = j < 7 ? in + (r16 + j) * PITCH + c0
+                                    : (res ? res + r16 * PITCH + c0 : in + (r16 + 6) * PITCH + c0);
+                }
+                const int tl = s0 - 3 * (l + 1);   // time of output row 0
+                f4v acc[NT];
+#pragma unroll
+                for (int m = 0; m < NT; ++m) acc[m] = bias(l + 1);
+#pragma unroll
+                for (int s = 0; s < 4; ++s) {
+                    bf16x8 xv[NT];
+#pragma unroll
+                    for (int m = 0; m < NT; ++m) xv[m] = *(const bf16x8*)(bsrc[s] + 16 * m * PITCH);
+#pragma unroll
+                    for (int m = 0; m < NT; ++m)
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[l][s], xv[m], acc[m], 0, 0, 0);
+                }
+#pragma unroll
+                for (int m = 0; m < NT; ++m) {
+                    const int q0 = 16 * m, t0 = tl + q0;
+                    const uint2 packed = finish_tile(acc[m], t0 < 0 || t0 + 15 >= L, t0 + r16, L);
                     if (out) {
-                        const uint32_t lo = (__float_as_uint(v[0]) >> 16) | (__float_as_uint(v[1]) & 0xFFFF0000u);
-                        const uint32_t hi = (__float_as_uint(v[2]) >> 16) | (__float_as_uint(v[3]) & 0xFFFF0000u);
-                        *(uint2*)(out + (q + GUARD) * PITCH + 4 * g) = make_uint2(lo, hi);
-                    } else if (t >= t0 && t < t0 + T && t < L) {
-#pragma unroll
-                        for (int r = 0; r < 4; ++r) gsum[r] += v[r];
+                        *(uint2*)(out + (TAIL + q0 + r16) * PITCH + 4 * g) = packed;
+                    } else {
+                        gs[0] += __uint_as_float(packed.x << 16);
+                        gs[1] += __uint_as_float(packed.x & 0xFFFF0000u);
+                        gs[2] += __uint_as_float(packed.y << 16);
+                        gs[3] += __uint_as_float(packed.y & 0xFFFF0000u);
                     }
                 }
             };
-            layer(0, bufA, bufB, nullptr);   // block 0 conv1: h0 -> r1
-            __syncthreads();
-            layer(1, bufB, bufC, bufA);      // block 0 conv2 + h0: -> h2
-            __syncthreads();
-            layer(2, bufC, bufB, nullptr);   // block 1 conv1: h2 -> r3
-            __syncthreads();
-            layer(3, bufB, nullptr, bufC);   // block 1 conv2 + h2: -> GAP
-            __syncthreads();
+            conv(0, buf(0), nullptr, buf(1));   // block 0 conv1
+            wave_lds_sync();
+            conv(1, buf(1), buf(0), buf(2));    // block 0 conv2 + block input
+            wave_lds_sync();
+            conv(2, buf(2), nullptr, buf(3));   // block 1 conv1
+            wave_lds_sync();
+            conv(3, buf(3), buf(2), nullptr);   // block 1 conv2 + block input -> average
+            wave_lds_sync();
+
+            // carry the last TAIL rows of every buffer, and of the input, to the front
+            for (int e = lane; e < 4 * TAIL * 3; e += 64) {
+                const int b = e / (TAIL * 3), u = e % (TAIL * 3);
+                const int off = (u / 3) * PITCH + (u % 3) * 8;
+                *(uint4*)(buf(b) + off) = *(const uint4*)(buf(b) + T * PITCH + off);
+            }
+            if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = xs[(lane / TAIL) * G::XN + T + lane % TAIL];
+            wave_lds_sync();
         }
-        // GAP: sum the 16 rows held by the lanes of each group, then the waves
+        // global average (sum over the lane's rows, then over the 16 lanes of
+        // each channel group) and FC, in a fixed order
 #pragma unroll
         for (int r = 0; r < 4; ++r)
-            for (int off = 8; off > 0; off >>= 1) gsum[r] += __shfl_xor(gsum[r], off);
-        if (r16 == 0) {
 #pragma unroll
-            for (int r = 0; r < 4; ++r) gpart[wave * C + 4 * g + r] = gsum[r];
-        }
-        __syncthreads();
-        if (tid == 0) {
-            float z = a.fc_b;
-            for (int c = 0; c < C; ++c) {
-                const float tot = ((gpart[c] + gpart[C + c]) + gpart[2 * C + c]) + gpart[3 * C + c];
-                z += tot / (float)L * a.fc_w[c];
-            }
-            a.logits[win] = z;
-        }
-        __syncthreads();
+            for (int off = 1; off < 16; off <<= 1) gs[r] += __shfl_xor(gs[r], off);
+        float z = 0.f;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) z += gs[r] / (float)L * fcw[r];
+        z += __shfl_xor(z, 16);
+        z += __shfl_xor(z, 32);
+        if (lane == 0) a.logits[win] = fcb + z;
+        wave_lds_sync();
     }
 }
 

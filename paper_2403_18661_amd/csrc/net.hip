@@ -225,6 +225,13 @@ uint8_t host_e4m3_bits(double v) {
 
 enum Buf { BX = 0, BR = 1, BP = 2 };
 
+// (rows per step, activation row pitch in BF16 elements) of the whole-network
+// kernel's candidates (autotuned)
+struct FusedShape {
+    int rows, pitch;
+};
+constexpr FusedShape kFusedSteps[] = {{32, 24}, {48, 24}, {64, 24}, {48, 40}, {48, 48}, {32, 48}};
+
 struct ConvOp {
     int c_in, c_out, kw, s, l_in, l_out, relu;
     int in_buf, out_buf, res_buf;  // res_buf < 0: none
@@ -320,8 +327,10 @@ struct af_net {
     // whole-network persistent kernel for the 16-channel two-block net (BF16)
     bool fused_ok = false, fused_on = false;
     int n_cu = 0;
+    int fused_cand = 1;             // index into kFusedSteps: rows per step
     uint16_t* d_wfused = nullptr;   // [4][16][128]
-    float* d_bfused = nullptr;      // [4][16]
+    float* d_bfused = nullptr;      // [5][16]: stem, convs
+    float* d_sfused = nullptr;      // [16][16] stem weights by k = input channel * 8 + tap
     std::vector<Rec> recs;
     std::vector<int64_t> layer_macs;  // per window: stem, convs..., gap/fc
 };
@@ -351,6 +360,7 @@ void free_net(af_net* n) {
     if (n->d_gn) (void)hipFree(n->d_gn);
     if (n->d_wfused) (void)hipFree(n->d_wfused);
     if (n->d_bfused) (void)hipFree(n->d_bfused);
+    if (n->d_sfused) (void)hipFree(n->d_sfused);
     delete n;
 }
 }  // namespace
@@ -584,8 +594,15 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
     const bool tiny = !groups && d->in_ch == 2 && d->stem_ch == 16 && d->stem_stride == 1 && !d->stem_pool &&
                       d->n_stages == 1 && d->widths[0] == 16 && d->blocks[0] == 2 && net->ops.size() == 4;
     if (tiny && prec == AF_BF16) {
+        // conv weights [layer][out][k = tap * 16 + in]; the eighth tap of the
+        // second conv of each block is the identity (it adds the block input)
         std::vector<uint16_t> wf(4 * 16 * 128, 0);
-        std::vector<float> bf(4 * 16);
+        std::vector<float> bf(5 * 16), sf(16 * 16, 0.f);
+        for (int o = 0; o < 16; ++o) {
+            for (int c = 0; c < 2; ++c)
+                for (int j = 0; j < 7; ++j) sf[o * 16 + c * 8 + j] = stem[((size_t)o * 2 + c) * 7 + j];
+            bf[o] = stem[(size_t)16 * 2 * 7 + o];
+        }
         for (int l = 0; l < 4; ++l) {
             const ConvOp& op = net->ops[l];
             for (int o = 0; o < 16; ++o) {
@@ -593,11 +610,13 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
                     for (int c = 0; c < 16; ++c)
                         wf[((size_t)l * 16 + o) * 128 + j * 16 + c] =
                             host_bf16_bits(wfold[op.w_off + ((size_t)o * 7 + j) * 16 + c]);
-                bf[l * 16 + o] = bias[op.b_off + o];
+                if (l == 1 || l == 3) wf[((size_t)l * 16 + o) * 128 + 7 * 16 + o] = host_bf16_bits(1.0);
+                bf[(l + 1) * 16 + o] = bias[op.b_off + o];
             }
         }
         if (!upload((void**)&net->d_wfused, wf.data(), wf.size() * 2) ||
-            !upload((void**)&net->d_bfused, bf.data(), bf.size() * 4)) {
+            !upload((void**)&net->d_bfused, bf.data(), bf.size() * 4) ||
+            !upload((void**)&net->d_sfused, sf.data(), sf.size() * 4)) {
             free_net(net);
             set_error("device allocation/upload of the fused weights failed");
             return AF_ENOMEM;
@@ -678,6 +697,27 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
                         int64_t n_windows, const int64_t* shift, int64_t wrap, const int64_t* table, int n_entries,
                         float* logits, void* ws, size_t ws_bytes, hipStream_t s);
 
+// The whole-network kernel with `cand`'s rows per step (kFusedSteps), on a
+// persistent grid of as many one-wavefront workgroups as fit the device at
+// once (each walks windows blockIdx.x, + gridDim.x, ...).
+bool launch_fused(int cand, int n_cu, const FusedTinyArgs& fa, hipStream_t s) {
+    auto go = [&](auto kernel) -> bool {
+        int occ = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess || occ < 1) occ = 1;
+        const int64_t grid = std::min<int64_t>(fa.n_windows, (int64_t)occ * n_cu);
+        hipLaunchKernelGGL(kernel, dim3((unsigned)grid), dim3(64), 0, s, fa);
+        return hipPeekAtLastError() == hipSuccess;
+    };
+    switch (cand) {
+        case 0: return go(fused_tiny_bf16_kernel<32, 24>);
+        case 1: return go(fused_tiny_bf16_kernel<48, 24>);
+        case 2: return go(fused_tiny_bf16_kernel<64, 24>);
+        case 3: return go(fused_tiny_bf16_kernel<48, 40>);
+        case 4: return go(fused_tiny_bf16_kernel<48, 48>);
+        default: return go(fused_tiny_bf16_kernel<32, 48>);
+    }
+}
+
 // GroupNorm of nb windows of [L][C] FP32 activations (one workgroup each);
 // gamma and beta at gn_off of the net's table.
 void launch_gn(const af_net* net, const void* in, const void* res, void* out, size_t gn_off, int L, int C, int relu,
@@ -741,17 +781,17 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         sa.table = table; sa.n_entries = n_entries;
         for (int c = 0; c < 4; ++c) sa.shift[c] = c < n_ch ? shift[c] : 0;
         sa.n_ch = (int)n_ch; sa.window = window;
-        sa.w = net->d_stem; sa.b = net->d_stem + (size_t)16 * 2 * 7;
-        fa.wconv = net->d_wfused; fa.bconv = net->d_bfused; fa.fc_w = net->d_fc; fa.fc_b = net->fc_b;
+        fa.wstem = net->d_sfused; fa.wconv = net->d_wfused; fa.bias = net->d_bfused; fa.fc = net->d_fc;
         fa.logits = logits; fa.n_windows = n_windows;
-        const int64_t grid = std::min<int64_t>(n_windows, (int64_t)2 * net->n_cu);
         af_net::Rec r{1, n_windows, net->macs, nullptr, nullptr};
         if (net->profiling) {
             if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
                 hipEventRecord(r.a, s) != hipSuccess) { set_error("profiling event failed"); return AF_EHIP; }
         }
-        hipLaunchKernelGGL(fused_tiny_bf16_kernel, dim3((unsigned)grid), dim3(256), 0, s, fa);
-        AF_LAUNCHED();
+        if (!launch_fused(net->fused_cand, net->n_cu, fa, s)) {
+            set_error("whole-network kernel launch failed: %s", hipGetErrorString(hipGetLastError()));
+            return AF_EHIP;
+        }
         if (net->profiling) {
             if (hipEventRecord(r.b, s) != hipSuccess) { set_error("profiling event failed"); return AF_EHIP; }
             mnet0->recs.push_back(r);
@@ -1066,7 +1106,42 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
     AF_HIP(hipEventCreate(&e1));
     int64_t changed = 0;
     af_status result = AF_OK;
+    if (net->fused_ok) {
+        // rows per step of the whole-network kernel: `batch` windows of the
+        // zeroed workspace read as a two-channel series (windows 2048 apart)
+        const int64_t n = (batch - 1) * 2048 + net->desc.window;
+        FusedTinyArgs fa{};
+        StemArgs& sa = fa.st;
+        sa.y = (const float*)ws; sa.ld_y = n; sa.n = n; sa.stride = 2048;
+        sa.n_ch = 2; sa.window = net->desc.window;
+        fa.wstem = net->d_sfused; fa.wconv = net->d_wfused; fa.bias = net->d_bfused; fa.fc = net->d_fc;
+        fa.logits = (float*)ws + 2 * n; fa.n_windows = batch;
+        AF_CHECK_ARG((size_t)(2 * n + batch) * sizeof(float) <= 3 * bb, "workspace too small for batch %lld",
+                     (long long)batch);
+        int best = net->fused_cand;
+        float best_ms = 1e30f;
+        for (int ci = 0; ci < (int)(sizeof(kFusedSteps) / sizeof(kFusedSteps[0])) && result == AF_OK; ++ci) {
+            bool ok = launch_fused(ci, net->n_cu, fa, s);   // warm-up
+            (void)hipEventRecord(e0, s);
+            for (int rep = 0; rep < 3 && ok; ++rep) ok = launch_fused(ci, net->n_cu, fa, s);
+            (void)hipEventRecord(e1, s);
+            hipError_t err = ok ? hipEventSynchronize(e1) : hipGetLastError();
+            float ms = 0.f;
+            if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+            if (err != hipSuccess) {
+                set_error("autotune: timing failed: %s", hipGetErrorString(err));
+                result = AF_EHIP;
+                break;
+            }
+            if (ms < best_ms) { best_ms = ms; best = ci; }
+        }
+        if (result == AF_OK && best != net->fused_cand) {
+            net->fused_cand = best;
+            ++changed;
+        }
+    }
     for (ConvOp& op : net->ops) {
+        if (result != AF_OK) break;
         if (op.cands.size() < 2) continue;
         int best = op.cand;
         float best_ms = 1e30f;
@@ -1293,4 +1368,23 @@ extern "C" af_status af_net_calibrate(af_net* net, const float* y, int64_t n_ch,
     }
     net->fc_b = fcb;
     return done(AF_OK);
+}
+
+extern "C" af_status af_net_fused_tile(const af_net* net, int32_t* rows, int32_t* n_candidates, int32_t* chosen) {
+    clear_error();
+    AF_CHECK_ARG(net && rows && n_candidates && chosen, "bad arguments");
+    AF_CHECK_ARG(net->fused_ok, "this net has no whole-network kernel");
+    *rows = kFusedSteps[net->fused_cand].rows;
+    *n_candidates = (int32_t)(sizeof(kFusedSteps) / sizeof(kFusedSteps[0]));
+    *chosen = net->fused_cand;
+    return AF_OK;
+}
+
+extern "C" af_status af_net_set_fused_tile(af_net* net, int32_t chosen) {
+    clear_error();
+    AF_CHECK_ARG(net && net->fused_ok, "this net has no whole-network kernel");
+    AF_CHECK_ARG(chosen >= 0 && chosen < (int32_t)(sizeof(kFusedSteps) / sizeof(kFusedSteps[0])),
+                 "candidate %d out of range", (int)chosen);
+    net->fused_cand = chosen;   // kernel arguments only: graphs captured earlier keep theirs
+    return AF_OK;
 }

@@ -178,6 +178,29 @@ def test_fused_tiny_matches_layer_path():
     assert np.abs(a - ref).max() < EMU_TOL["bf16"]
 
 
+def test_fused_step_candidates_same_logits():
+    # every rows-per-step candidate of the whole-network kernel gives the same
+    # logits bit for bit (windows of every length class: one, a few, ragged)
+    P = need_gpu()
+    banner("fused tiny step candidates")
+    params = make_params(TINY_ARCH, seed=30)
+    y = dev(series(3072 + 128 * 70 + 5, seed=31))
+    net = P.Net(TINY_ARCH, params, "bf16")
+    rows, n_cand, chosen = net.fused_tile()
+    ref = net.score_windows(y, 128).cpu().numpy()
+    for c in range(n_cand):
+        net.set_fused_tile(c)
+        assert net.fused_tile()[0] in (32, 48, 64)
+        np.testing.assert_array_equal(net.score_windows(y, 128).cpu().numpy(), ref)
+        np.testing.assert_array_equal(net.score_windows(y, 128, 1).cpu().numpy(), ref[:1])
+    net.set_fused_tile(chosen)
+    changed = net.autotune(batch=256)
+    print(f"fused rows per step: {net.fused_tile()}, autotune changed {changed}")
+    np.testing.assert_array_equal(net.score_windows(y, 128).cpu().numpy(), ref)
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        net.set_fused_tile(n_cand)
+
+
 def test_fused_unavailable_for_fp32():
     P = need_gpu()
     net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=1), "f32")
