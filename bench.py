@@ -389,9 +389,6 @@ def main():
     from synth.workloads import hour_strain, PSD_LEN
 
     arch = RESNET_ARCH
-    if args.timeslide_only:
-        print(json.dumps({"timeslide": timeslide_leg(args, P, log)}), flush=True)
-        return
     if args.calib_copy_mb > 0:
         src = torch.ones(args.calib_copy_mb << 18, dtype=torch.float32, device="cuda")
         dst = torch.empty_like(src)
@@ -400,6 +397,9 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy of {args.calib_copy_mb} MiB done")
         del src, dst
+    if args.timeslide_only:
+        print(json.dumps({"timeslide": timeslide_leg(args, P, log)}), flush=True)
+        return
     log("generating 1 h workload")
     x, inj = hour_strain(seed=0, n_windows=args.windows)
     params = make_params(arch, seed=0)

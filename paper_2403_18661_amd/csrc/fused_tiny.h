@@ -2,33 +2,42 @@
 // BasicBlocks of 16 channels, GAP, FC) in BF16: one wavefront per window,
 // persistent over windows.
 //
+// Workgroups take windows from a queue: the first window of workgroup b is
+// window b, the next ones come from an atomic counter (cleared before the
+// launch), so the launch may hold more workgroups than fit the device at once
+// without leaving late ones a full share of the work.
+//
 // A wavefront walks its window in steps of T time rows.  In step k the stem
 // produces rows [kT, kT + T) and conv layer l (l = 1..4) the rows
 // [kT - 3l, kT + T - 3l).  A k7 conv reads 3 rows beyond its output on each
 // side; the layer before produced them in this step or in the previous one,
 // whose last 6 rows every buffer carries to its front, so no row is computed
 // twice.  Rows outside the window are forced to zero (the per-layer zero
-// padding of the unfused network); a 16-row tile wholly outside is not
-// computed.  Activations stay in the wavefront's LDS (BF16), weights in
-// registers.  With one wavefront per workgroup, ordering its own LDS accesses
-// between layers needs no barrier, only a wait for its LDS operations
-// (wave_lds_sync); the next step's input loads stay in flight meanwhile.
+// padding of the unfused network); only the steps that reach outside the
+// window (the first and the last) test rows at all.  Activations stay in the
+// wavefront's LDS (BF16), weights in registers.  With one wavefront per
+// workgroup, ordering its own LDS accesses between layers needs no barrier,
+// only a wait for its LDS operations (wave_lds_sync); the next step's input
+// loads stay in flight meanwhile.
 //
 // Every layer runs on the matrix cores, transposed (D[channel][time] =
-// W[channel][k] X[k][time]) so that a lane ends with four consecutive
-// channels of one time row:
+// W[channel][k] X[k][time]) in 16-row tiles, so that a lane ends with four
+// consecutive channels of one time row:
 //  - stem: FP32 16x16x4 MFMAs over k = input channel x 8 + tap (the eighth
 //    tap has weight 0), FP32 weights and input;
 //  - convs: BF16 16x16x32 MFMAs over k = tap x 16 + channel.  The eighth tap
 //    pads K from 112 to 128; in the second conv of a block it carries the
 //    residual (identity weights times the block input's row), which is then
-//    summed in FP32 with the products;
+//    summed in FP32 with the products.  Each k-step's operands are read from
+//    LDS while the previous k-step's MFMAs run;
 //  - the bias is the accumulator's initial value.
 // Outputs are rounded to BF16 (hardware round-to-nearest-even) and then
 // passed through ReLU as packed 16-bit integers (a BF16 value is negative iff
 // its bit pattern is, and rounding commutes with max(., 0)); the second
 // block's output goes to the global average, then FC.
 #pragma once
+#include <type_traits>
+
 #include "net_kernels.h"
 
 namespace afm {
@@ -41,6 +50,7 @@ struct FusedTinyArgs {
     const float* fc;           // [16] weights, then the bias
     float* logits;
     int64_t n_windows;
+    unsigned int* next;        // window queue counter (zero at launch)
 };
 
 // Waits for this wavefront's outstanding LDS operations and keeps the
@@ -49,18 +59,18 @@ struct FusedTinyArgs {
 __device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
 
 // BF16 pair: round to nearest even, then ReLU on the bit patterns (one packed
-// signed 16-bit max); zero where `keep` is false.
+// signed 16-bit max).
 typedef short short2v __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t relu_bf16x2(float lo, float hi) {
     const short2v v = __builtin_bit_cast(short2v, pack_bf16x2(lo, hi));
     return __builtin_bit_cast(uint32_t, __builtin_elementwise_max(v, short2v{0, 0}));
 }
-// A tile's four outputs (channels 4g .. 4g + 3 of one time row) as stored:
-// rows whose time lies outside [0, L) become zero.  `edge` (the same on every
-// lane) says whether the tile reaches outside; only then is the row tested.
-__device__ __forceinline__ uint2 finish_tile(const f4v& acc, bool edge, int t, int L) {
+// A tile's four outputs (channels 4g .. 4g + 3 of one time row t) as stored;
+// with EDGE, zero when t lies outside [0, L).
+template <bool EDGE>
+__device__ __forceinline__ uint2 finish_tile(const f4v& acc, int t, int L) {
     uint2 p = make_uint2(relu_bf16x2(acc[0], acc[1]), relu_bf16x2(acc[2], acc[3]));
-    if (edge && (t < 0 || t >= L)) p = make_uint2(0u, 0u);
+    if (EDGE && (t < 0 || t >= L)) p = make_uint2(0u, 0u);
     return p;
 }
 
@@ -72,26 +82,36 @@ struct Geo {
     static constexpr int ROWS = T + TAIL;      // rows per activation buffer
     static constexpr int BUF = ROWS * PITCH;   // elements per buffer
     static constexpr int XN = T + TAIL;        // input samples per channel
-    static constexpr int LDS = 4 * BUF * 2 + 2 * XN * 4 + 5 * C * 4;
 };
 }  // namespace fused_tiny
 
+// Element offset of channel half `hf` (8 channels, 16 bytes) of activation
+// row t.  SWZ: 64-byte rows whose 16-byte units are XOR-swizzled by
+// (t / 2) & 3 (the layout the MFMA operand reads meet without LDS bank
+// conflicts); otherwise plain rows of PITCH elements.
+template <int PITCH, bool SWZ>
+__device__ __forceinline__ int act_off(int t, int hf) {
+    return t * PITCH + 8 * (SWZ ? (hf ^ ((t >> 1) & 3)) : hf);
+}
+
 // T: time rows per step; PITCH: BF16 elements per stored activation row (16
-// channels and padding, which sets the LDS bank pattern of the operand reads)
-template <int T, int PITCH>
+// channels and padding); SWZ: the swizzled 64-byte rows (PITCH 32).
+// Sample indices are 32-bit: the caller guarantees n_ch * ld_y < 2^31.
+template <int T, int PITCH, bool SWZ>
 __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a) {
     using namespace fused_tiny;
     using G = Geo<T, PITCH>;
-    static_assert(T % 16 == 0 && (T <= 64 || T % 64 == 0), "steps of whole 16-row tiles");
-    constexpr int NT = T / 16;                  // row tiles per layer and step
+    static_assert(!SWZ || (PITCH == 32 && T % 8 == 0), "the swizzle needs 4 units per row and whole periods per step");
+    constexpr int UPR = PITCH / 8;              // 16-byte units per stored row
+    static_assert(T % 16 == 0 && T <= 64, "steps of whole 16-row tiles");
+    constexpr int NT = T / 16;                  // 16-row tiles per step
     __shared__ __attribute__((aligned(16))) uint16_t act[4 * G::BUF];   // stem, conv 1, conv 2, conv 3 outputs
     __shared__ float xs[2 * G::XN];
     __shared__ __attribute__((aligned(16))) float sbias[5 * C];   // read per layer and step: fewer live registers
     const int lane = threadIdx.x, g = lane >> 4, r16 = lane & 15;
     const int L = a.st.window;
-    const int64_t ld = a.st.ld_y;
 
-    // weights and biases for the kernel's lifetime
+    // weights for the kernel's lifetime
     float ws[4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) ws[s] = a.wstem[r16 * 16 + 4 * s + g];
@@ -103,63 +123,63 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
             wa[l][s] = *(const bf16x8*)(a.wconv + ((size_t)l * C + r16) * 128 + 32 * s + 8 * g);
     for (int e = lane; e < 5 * C; e += 64) sbias[e] = a.bias[e];
     auto bias = [&](int l) { return *(const f4v*)(sbias + l * C + 4 * g); };
-    float fcw[4];
-#pragma unroll
-    for (int r = 0; r < 4; ++r) fcw[r] = a.fc[4 * g + r];
-    const float fcb = a.fc[C];
-
     auto buf = [&](int b) { return act + b * G::BUF; };
     const int nsteps = (L + 12 + T - 1) / T;
 
-    for (int64_t win = blockIdx.x; win < a.n_windows; win += gridDim.x) {
+    int64_t win = blockIdx.x;
+    while (win < a.n_windows) {
+        // the window after this one, asked for now and used at the end
+        unsigned int ticket = 0;
+        if (lane == 0) ticket = atomicAdd(a.next, 1u);
+        // sample t of channel c is y[e0[c] + t], less `wrap` from t = lim[c] on
         const WinAddr wad = window_addr(a.st, win);
+        int e0[2], lim[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            e0[c] = (int)(c * a.st.ld_y + wad.base + wad.start[c]);
+            lim[c] = wad.wrap > 0 ? (int)(wad.wrap - wad.start[c]) : 0x7FFFFFFF;
+        }
+        const int wrap = (int)wad.wrap;
         auto sample = [&](int c, int t) -> float {
-            return (t >= 0 && t < L) ? a.st.y[c * ld + window_sample(wad, c, t)] : 0.f;
+            const int e = e0[c] + t - (t >= lim[c] ? wrap : 0);
+            return (t >= 0 && t < L) ? a.st.y[e] : 0.f;
         };
         // window start: the carried rows lie before the window (zero); the
         // input's carried samples are those of times -3 .. 2
-        for (int e = lane; e < 4 * TAIL * 3; e += 64) {
-            const int b = e / (TAIL * 3), u = e % (TAIL * 3);
-            *(uint4*)(buf(b) + (u / 3) * PITCH + (u % 3) * 8) = make_uint4(0u, 0u, 0u, 0u);
+        for (int e = lane; e < 4 * TAIL * UPR; e += 64) {
+            const int b = e / (TAIL * UPR), u = e % (TAIL * UPR);
+            *(uint4*)(buf(b) + (u / UPR) * PITCH + (u % UPR) * 8) = make_uint4(0u, 0u, 0u, 0u);
         }
         if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = sample(lane / TAIL, lane % TAIL - 3);
-        // samples of times s0 + 3 .. s0 + T + 2 of step 0 (T / 64 per lane and channel)
-        constexpr int PER = T >= 64 ? T / 64 : 1;
-        float nx[2][PER];
+        // samples of times s0 + 3 .. s0 + T + 2 of step 0
+        float nx[2];
 #pragma unroll
-        for (int c = 0; c < 2; ++c)
-#pragma unroll
-            for (int p = 0; p < PER; ++p) nx[c][p] = (lane + 64 * p < T) ? sample(c, 3 + lane + 64 * p) : 0.f;
+        for (int c = 0; c < 2; ++c) nx[c] = lane < T ? sample(c, 3 + lane) : 0.f;
         f4v gs = {0.f, 0.f, 0.f, 0.f};
 
-        for (int k = 0; k < nsteps; ++k) {
+        // one step; EDGE (the first and last steps) zeroes rows outside the window
+        auto step = [&](const int k, auto edge_tag) {
+            constexpr bool EDGE = decltype(edge_tag)::value;
             const int s0 = k * T;
-#pragma unroll
-            for (int c = 0; c < 2; ++c)
-#pragma unroll
-                for (int p = 0; p < PER; ++p)
-                    if (lane + 64 * p < T) xs[c * G::XN + TAIL + lane + 64 * p] = nx[c][p];
+            if (lane < T) {
+                xs[TAIL + lane] = nx[0];
+                xs[G::XN + TAIL + lane] = nx[1];
+            }
             // the next step's samples are loaded now and stored a step later
             if (k + 1 < nsteps) {
 #pragma unroll
-                for (int c = 0; c < 2; ++c)
-#pragma unroll
-                    for (int p = 0; p < PER; ++p)
-                        nx[c][p] = (lane + 64 * p < T) ? sample(c, s0 + T + 3 + lane + 64 * p) : 0.f;
+                for (int c = 0; c < 2; ++c) nx[c] = lane < T ? sample(c, s0 + T + 3 + lane) : 0.f;
             }
             wave_lds_sync();
 
             // ---- stem: rows s0 .. s0 + T - 1 into buffer 0 (rows TAIL ..)
             {
-                const int j0 = 4 * 0 + g, j1 = 4 + g;   // taps of the even / odd k-steps
                 const float* xb[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const int j = (s & 1) ? j1 : j0;
+                    const int j = 4 * (s & 1) + g;   // k = 4s + g: input channel s / 2, tap j
                     xb[s] = xs + (s >> 1) * G::XN + r16 + (j == 7 ? 6 : j);   // tap 7: any sample, weight 0
                 }
-                // the tiles' accumulation chains interleaved; tiles past the
-                // window are computed too (their rows are then zeroed)
                 f4v acc[NT];
 #pragma unroll
                 for (int m = 0; m < NT; ++m) acc[m] = bias(0);
@@ -171,12 +191,11 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
 #pragma unroll
                     for (int m = 0; m < NT; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ws[s], xv[m], acc[m], 0, 0, 0);
                 }
+                // row TAIL + 16m + r16 keeps the swizzle phase of TAIL + r16
+                const int so = act_off<PITCH, SWZ>(TAIL + r16, g >> 1) + 4 * (g & 1);
 #pragma unroll
-                for (int m = 0; m < NT; ++m) {
-                    const int t0 = s0 + 16 * m;
-                    *(uint2*)(buf(0) + (TAIL + 16 * m + r16) * PITCH + 4 * g) =
-                        finish_tile(acc[m], t0 + 15 >= L, t0 + r16, L);
-                }
+                for (int m = 0; m < NT; ++m)
+                    *(uint2*)(buf(0) + so + 16 * m * PITCH) = finish_tile<EDGE>(acc[m], s0 + 16 * m + r16, L);
             }
             wave_lds_sync();
 
@@ -185,29 +204,33 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
                 const uint16_t* bsrc[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    const int j = 2 * s + (g >> 1), c0 = 8 * (g & 1);
-                    bsrc[s] = j < 7 ? in + (r16 + j) * PITCH + c0
-                                    : (res ? res + r16 * PITCH + c0 : in + (r16 + 6) * PITCH + c0);
+                    const int j = 2 * s + (g >> 1), hf = g & 1;
+                    bsrc[s] = j < 7 ? in + act_off<PITCH, SWZ>(r16 + j, hf)
+                                    : (res ? res + act_off<PITCH, SWZ>(r16, hf) : in + act_off<PITCH, SWZ>(r16 + 6, hf));
                 }
-                const int tl = s0 - 3 * (l + 1);   // time of output row 0
                 f4v acc[NT];
 #pragma unroll
                 for (int m = 0; m < NT; ++m) acc[m] = bias(l + 1);
+                bf16x8 xv[2][NT];
+#pragma unroll
+                for (int m = 0; m < NT; ++m) xv[0][m] = *(const bf16x8*)(bsrc[0] + 16 * m * PITCH);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
-                    bf16x8 xv[NT];
+                    if (s < 3) {
 #pragma unroll
-                    for (int m = 0; m < NT; ++m) xv[m] = *(const bf16x8*)(bsrc[s] + 16 * m * PITCH);
+                        for (int m = 0; m < NT; ++m) xv[(s + 1) & 1][m] = *(const bf16x8*)(bsrc[s + 1] + 16 * m * PITCH);
+                    }
 #pragma unroll
                     for (int m = 0; m < NT; ++m)
-                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[l][s], xv[m], acc[m], 0, 0, 0);
+                        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wa[l][s], xv[s & 1][m], acc[m], 0, 0, 0);
                 }
+                const int tl = s0 - 3 * (l + 1);   // time of output row 0
+                const int so = act_off<PITCH, SWZ>(TAIL + r16, g >> 1) + 4 * (g & 1);
 #pragma unroll
                 for (int m = 0; m < NT; ++m) {
-                    const int q0 = 16 * m, t0 = tl + q0;
-                    const uint2 packed = finish_tile(acc[m], t0 < 0 || t0 + 15 >= L, t0 + r16, L);
+                    const uint2 packed = finish_tile<EDGE>(acc[m], tl + 16 * m + r16, L);
                     if (out) {
-                        *(uint2*)(out + (TAIL + q0 + r16) * PITCH + 4 * g) = packed;
+                        *(uint2*)(out + so + 16 * m * PITCH) = packed;
                     } else {
                         gs[0] += __uint_as_float(packed.x << 16);
                         gs[1] += __uint_as_float(packed.x & 0xFFFF0000u);
@@ -226,13 +249,21 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
             wave_lds_sync();
 
             // carry the last TAIL rows of every buffer, and of the input, to the front
-            for (int e = lane; e < 4 * TAIL * 3; e += 64) {
-                const int b = e / (TAIL * 3), u = e % (TAIL * 3);
-                const int off = (u / 3) * PITCH + (u % 3) * 8;
+            for (int e = lane; e < 4 * TAIL * UPR; e += 64) {   // whole rows: T keeps the swizzle phase
+                const int b = e / (TAIL * UPR), u = e % (TAIL * UPR);
+                const int off = (u / UPR) * PITCH + (u % UPR) * 8;
                 *(uint4*)(buf(b) + off) = *(const uint4*)(buf(b) + T * PITCH + off);
             }
             if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = xs[(lane / TAIL) * G::XN + T + lane % TAIL];
             wave_lds_sync();
+        };
+        for (int k = 0; k < nsteps; ++k) {
+            // a step reaches outside the window when layer 4 starts before time
+            // 0 or the stem ends past the last sample
+            if (k * T < 12 || (k + 1) * T > L)
+                step(k, std::true_type{});
+            else
+                step(k, std::false_type{});
         }
         // global average (sum over the lane's rows, then over the 16 lanes of
         // each channel group) and FC, in a fixed order
@@ -242,11 +273,12 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
             for (int off = 1; off < 16; off <<= 1) gs[r] += __shfl_xor(gs[r], off);
         float z = 0.f;
 #pragma unroll
-        for (int r = 0; r < 4; ++r) z += gs[r] / (float)L * fcw[r];
+        for (int r = 0; r < 4; ++r) z += gs[r] / (float)L * a.fc[4 * g + r];
         z += __shfl_xor(z, 16);
         z += __shfl_xor(z, 32);
-        if (lane == 0) a.logits[win] = fcb + z;
+        if (lane == 0) a.logits[win] = a.fc[C] + z;
         wave_lds_sync();
+        win = (int64_t)gridDim.x + (int64_t)__shfl(ticket, 0);
     }
 }
 

@@ -229,8 +229,10 @@ enum Buf { BX = 0, BR = 1, BP = 2 };
 // kernel's candidates (autotuned)
 struct FusedShape {
     int rows, pitch;
+    bool swz;
 };
-constexpr FusedShape kFusedSteps[] = {{32, 24}, {48, 24}, {64, 24}, {48, 40}, {48, 48}, {32, 48}};
+constexpr FusedShape kFusedSteps[] = {{32, 24, false}, {48, 24, false}, {64, 24, false},
+                                      {32, 32, true}, {48, 32, true}, {64, 32, true}};
 
 struct ConvOp {
     int c_in, c_out, kw, s, l_in, l_out, relu;
@@ -697,10 +699,13 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
                         int64_t n_windows, const int64_t* shift, int64_t wrap, const int64_t* table, int n_entries,
                         float* logits, void* ws, size_t ws_bytes, hipStream_t s);
 
-// The whole-network kernel with `cand`'s rows per step (kFusedSteps), on a
-// persistent grid of as many one-wavefront workgroups as fit the device at
-// once (each walks windows blockIdx.x, + gridDim.x, ...).
+// The whole-network kernel with candidate `cand` (kFusedSteps), on a
+// persistent grid of as many one-wavefront workgroups as the occupancy query
+// says fit the device at once; they take windows from the queue counter
+// fa.next, which a fill kernel clears first (no memset node in a captured
+// graph).
 bool launch_fused(int cand, int n_cu, const FusedTinyArgs& fa, hipStream_t s) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, s, (uint32_t*)fa.next, (int64_t)1, 0u);
     auto go = [&](auto kernel) -> bool {
         int occ = 0;
         if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&occ, kernel, 64, 0) != hipSuccess || occ < 1) occ = 1;
@@ -709,12 +714,12 @@ bool launch_fused(int cand, int n_cu, const FusedTinyArgs& fa, hipStream_t s) {
         return hipPeekAtLastError() == hipSuccess;
     };
     switch (cand) {
-        case 0: return go(fused_tiny_bf16_kernel<32, 24>);
-        case 1: return go(fused_tiny_bf16_kernel<48, 24>);
-        case 2: return go(fused_tiny_bf16_kernel<64, 24>);
-        case 3: return go(fused_tiny_bf16_kernel<48, 40>);
-        case 4: return go(fused_tiny_bf16_kernel<48, 48>);
-        default: return go(fused_tiny_bf16_kernel<32, 48>);
+        case 0: return go(fused_tiny_bf16_kernel<32, 24, false>);
+        case 1: return go(fused_tiny_bf16_kernel<48, 24, false>);
+        case 2: return go(fused_tiny_bf16_kernel<64, 24, false>);
+        case 3: return go(fused_tiny_bf16_kernel<32, 32, true>);
+        case 4: return go(fused_tiny_bf16_kernel<48, 32, true>);
+        default: return go(fused_tiny_bf16_kernel<64, 32, true>);
     }
 }
 
@@ -774,7 +779,8 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
     const int window = net->desc.window;
     const int64_t n_ch = net->desc.in_ch;
     af_net* mnet0 = const_cast<af_net*>(net);   // timing records only
-    if (net->fused_ok && net->fused_on) {
+    // the whole-network kernel indexes samples with 32 bits
+    if (net->fused_ok && net->fused_on && n_ch * ld_y < (1LL << 31)) {
         FusedTinyArgs fa{};
         StemArgs& sa = fa.st;
         sa.y = y; sa.ld_y = ld_y; sa.n = n; sa.stride = stride; sa.wrap = wrap; sa.first_window = 0;
@@ -783,6 +789,8 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         sa.n_ch = (int)n_ch; sa.window = window;
         fa.wstem = net->d_sfused; fa.wconv = net->d_wfused; fa.bias = net->d_bfused; fa.fc = net->d_fc;
         fa.logits = logits; fa.n_windows = n_windows;
+        AF_CHECK_ARG(ws && ws_bytes >= 256, "workspace too small: the whole-network kernel needs 256 bytes");
+        fa.next = (unsigned int*)ws;
         af_net::Rec r{1, n_windows, net->macs, nullptr, nullptr};
         if (net->profiling) {
             if (hipEventCreate(&r.a) != hipSuccess || hipEventCreate(&r.b) != hipSuccess ||
@@ -1116,7 +1124,8 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
         sa.n_ch = 2; sa.window = net->desc.window;
         fa.wstem = net->d_sfused; fa.wconv = net->d_wfused; fa.bias = net->d_bfused; fa.fc = net->d_fc;
         fa.logits = (float*)ws + 2 * n; fa.n_windows = batch;
-        AF_CHECK_ARG((size_t)(2 * n + batch) * sizeof(float) <= 3 * bb, "workspace too small for batch %lld",
+        fa.next = (unsigned int*)((float*)ws + 2 * n + batch);
+        AF_CHECK_ARG((size_t)(2 * n + batch + 1) * sizeof(float) <= 3 * bb, "workspace too small for batch %lld",
                      (long long)batch);
         int best = net->fused_cand;
         float best_ms = 1e30f;

@@ -15,6 +15,10 @@ whose warm-up and autotuning dispatches come first) are averaged.
     python -m paper_2403_18661_amd.profsum --trace DIR --fetch DIR --write DIR \\
         --calib-mb 1024 --group 'f32=conv_mfma_kernel<afm::PF32,@280' --cmd '...' --out FILE
 
+Optional ``--sq DIR`` runs (``--pmc`` with SQ_* counters, as many as one
+pass collects) add, per group, each counter summed over the group's
+dispatches and divided by their number.
+
 The summary ends with ``source_sha256`` of the kernel sources, so that a
 reader of the figures can tell whether the kernels changed since.
 """
@@ -69,7 +73,7 @@ def _calib(rows, calib_bytes):
     return calib_bytes / (float(big["Counter_Value"]) * 1024.0), float(big["Counter_Value"])
 
 
-def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12):
+def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=()):
     calib_bytes = calib_mb * 2 ** 20
     kt = _rows(trace, "kernel_trace.csv")
     ks = _rows(trace, "kernel_stats.csv")
@@ -91,6 +95,19 @@ def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12):
         fb = sum(float(r["Counter_Value"]) for r in _pick(fr, rx, last)) * 1024 * kf / last
         wb = sum(float(r["Counter_Value"]) for r in _pick(wr, rx, last)) * 1024 * kw / last
         lines.append(f"  {label:10s} {last:5d} {dur:9.4f} {fb / 1e6:10.2f} {wb / 1e6:10.2f} {fb + wb:26.0f}")
+    for d in sq_dirs:
+        rows = _rows(d, "counter_collection.csv")
+        lines.append("")
+        lines.append(f"SQ counters per dispatch ({os.path.basename(os.path.normpath(d))}):")
+        for label, rx, last in groups:
+            sel = [r for r in rows if rx.search(r["Kernel_Name"])]
+            ids = sorted({r["Dispatch_Id"] for r in sel}, key=int)[-last:]
+            agg = {}
+            for r in sel:
+                if r["Dispatch_Id"] in ids:
+                    agg[r["Counter_Name"]] = agg.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+            vals = "  ".join(f"{k} {v / len(ids):.4g}" for k, v in sorted(agg.items()))
+            lines.append(f"  {label:10s} {vals}")
     lines.append("")
     lines.append(f"--stats, top {top} kernels by total time (all dispatches of the run, incl. autotuning):")
     ks = sorted(ks, key=lambda r: -float(r["TotalDurationNs"]))[:top]
@@ -130,8 +147,9 @@ def main():
     ap.add_argument("--group", action="append", required=True)
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
+    ap.add_argument("--sq", action="append", default=[], help="directory of a --pmc run of SQ counters")
     a = ap.parse_args()
-    text = summarise(a.trace, a.fetch, a.write, a.calib_mb, _groups(a.group), a.cmd)
+    text = summarise(a.trace, a.fetch, a.write, a.calib_mb, _groups(a.group), a.cmd, sq_dirs=a.sq)
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
