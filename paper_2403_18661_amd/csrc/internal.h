@@ -10,6 +10,14 @@ af_status whiten_build_response(const double* psd, int64_t n_ch, int64_t n_psd, 
 af_status whiten_apply(const void* x, af_dtype xt, int64_t n_ch, int64_t n, int64_t ld_x, double prescale,
                        const float* resp, int64_t n_psd, int64_t psd_hop, int M, int64_t out_start, int64_t n_out,
                        float* y, int64_t ld_y, hipStream_t s);
+// Periodograms of n_seg segments x + i*step (FP64 physical strain times
+// prescale, periodic Hann) into pg [n_seg][n_ch][nperseg/2+1].
+af_status welch_pgrams(const double* x, int64_t n_ch, int64_t ld_x, double prescale, int64_t nperseg, int64_t step,
+                       int64_t n_seg, double* pg, hipStream_t s);
+// One-sided Welch PSD [n_ch][nperseg/2+1] from n_avg periodograms held in a
+// ring of R slots starting at slot `first`, summed in segment order.
+af_status welch_ring_average(const double* ring, int64_t n_ch, int64_t nperseg, int64_t R, int64_t first,
+                             int64_t n_avg, double fs, double* psd, hipStream_t s);
 // Score windows described by a device work table (see af_score_timeslides).
 af_status score_table(const af_net* net, const float* y, int64_t ld_y, int64_t n, int64_t stride,
                       int64_t n_windows, const int64_t* table, int n_entries, float* logits, void* ws,

@@ -8,7 +8,10 @@
 // background shares every segment spectrum between the PSDs that contain it.
 // Kernel 2 (average): PSD_j[c][k] = c_k / (fs sum w^2) * mean of the S
 // periodograms of background j, summed in segment order.
+#include <cmath>
+
 #include "fft_lds.h"
+#include "internal.h"
 
 namespace afm {
 
@@ -83,6 +86,25 @@ __global__ void welch_average_kernel(const double* __restrict__ pgram, int64_t n
     psd[idx] = s / (double)n_avg * scale * ck;
 }
 
+// Mean of n_avg periodograms held in a ring of R slots ([R][n_ch][F]),
+// starting at slot `first`, summed in segment order (the order
+// welch_average_kernel sums a contiguous run in).
+__global__ void welch_ring_average_kernel(const double* __restrict__ ring, int64_t n_ch, int F, int64_t R,
+                                          int64_t first, int64_t n_avg, double scale, double* __restrict__ psd) {
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= n_ch * F) return;
+    const int k = (int)(idx % F);
+    const int64_t stride = n_ch * (int64_t)F;
+    double s = 0.0;
+    for (int64_t i = 0; i < n_avg; ++i) {
+        int64_t slot = first + i;
+        if (slot >= R) slot -= R;
+        s += ring[slot * stride + idx];
+    }
+    const double ck = (k == 0 || k == F - 1) ? 1.0 : 2.0;
+    psd[idx] = s / (double)n_avg * scale * ck;
+}
+
 }  // namespace afm
 
 using namespace afm;
@@ -149,7 +171,43 @@ void dispatch_pgram(int logn, const void* x, int64_t n_ch, int64_t ld_x, double 
         default: launch_pgram<12, TX>(x, n_ch, ld_x, prescale, step, G, tw, pg, s); break;
     }
 }
+
+// 1 / (fs sum w^2) for the periodic Hann window, from its definition
+double welch_density_scale(double fs, int64_t nperseg) {
+    double sw2 = 0.0;
+    for (int64_t t = 0; t < nperseg; ++t) {
+        const double w = 0.5 - 0.5 * std::cos(6.283185307179586476925286766559 * (double)t / (double)nperseg);
+        sw2 += w * w;
+    }
+    return 1.0 / (fs * sw2);
+}
 }  // namespace
+
+namespace afm {
+af_status welch_pgrams(const double* x, int64_t n_ch, int64_t ld_x, double prescale, int64_t nperseg, int64_t step,
+                       int64_t n_seg, double* pg, hipStream_t s) {
+    if (n_seg <= 0) return AF_OK;
+    af_status st = ensure_tables(s);
+    if (st != AF_OK) return st;
+    const double* tw = twiddles_f64((int)nperseg);
+    AF_CHECK_ARG(tw && nperseg >= 256, "no twiddle table for nperseg = %lld", (long long)nperseg);
+    int logn = 0;
+    while ((1LL << logn) < nperseg) ++logn;
+    dispatch_pgram<double>(logn, x, n_ch, ld_x, prescale, step, n_seg, tw, pg, s);
+    AF_LAUNCHED();
+    return AF_OK;
+}
+
+af_status welch_ring_average(const double* ring, int64_t n_ch, int64_t nperseg, int64_t R, int64_t first,
+                             int64_t n_avg, double fs, double* psd, hipStream_t s) {
+    const int F = (int)(nperseg / 2 + 1);
+    const int64_t total = n_ch * F;
+    hipLaunchKernelGGL(welch_ring_average_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s, ring, n_ch,
+                       F, R, first, n_avg, welch_density_scale(fs, nperseg), psd);
+    AF_LAUNCHED();
+    return AF_OK;
+}
+}  // namespace afm
 
 extern "C" size_t af_psd_workspace_bytes(int64_t n_ch, int64_t nperseg, int64_t noverlap,
                                          int64_t psd_len, int64_t psd_hop, int64_t n_psd) {
@@ -185,15 +243,9 @@ extern "C" af_status af_psd_estimate(const void* x, af_dtype xt, int64_t n_ch, i
     else
         dispatch_pgram<float>(logn, x, n_ch, ld_x, prescale, g.step, g.n_seg_total, tw, pg, s);
     AF_LAUNCHED();
-    // sum of w^2 for the periodic Hann window, from its definition
-    double sw2 = 0.0;
-    for (int64_t t = 0; t < nperseg; ++t) {
-        double w = 0.5 - 0.5 * std::cos(6.283185307179586476925286766559 * (double)t / (double)nperseg);
-        sw2 += w * w;
-    }
     const int64_t total = n_psd * n_ch * g.F;
     hipLaunchKernelGGL(welch_average_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, s,
-                       pg, n_ch, g.F, n_psd, g.hop_seg, g.n_avg, 1.0 / (fs * sw2), psd);
+                       pg, n_ch, g.F, n_psd, g.hop_seg, g.n_avg, welch_density_scale(fs, nperseg), psd);
     AF_LAUNCHED();
     return AF_OK;
 }

@@ -3,8 +3,12 @@
 // ensemble of the paper's inference pipeline, Sec. VI, on one device).
 //
 // Per stream the device holds the recent raw strain (enough for the 64 s PSD
-// background plus filter context), the PSD and whitening response of the
-// current and next hop, the recent whitened output and the recent logits.
+// background plus filter context), a ring of the segment periodograms of the
+// current PSD background, the PSD and whitening response of the current and
+// next hop, the recent whitened output and the recent logits.  Each PSD hop
+// computes only the periodograms of the segments its background adds (8 of
+// 63 at the default 8 s hop) and averages the ring in segment order, which
+// gives the same PSD as a Welch estimate over the whole background.
 // Whitening runs in fixed 1 s output blocks at absolute positions and PSDs on
 // the fixed hop grid, so every result depends only on the stream's own data,
 // never on when its chunks arrived or what else shared the batch.  A tick
@@ -39,6 +43,8 @@ struct Stream {
     bool active = false;
     // device buffers
     double* raw = nullptr;     // [n_ch][cap_raw], absolute sample raw_base at column 0
+    double* pg_ring = nullptr; // [n_avg slots][n_ch][F]: periodogram of segment g in slot g % n_avg
+    int64_t seg_done = 0;      // segments (of the stream's global grid) whose periodogram was taken
     double* psd = nullptr;     // [2 slots][n_ch][F]
     float* resp = nullptr;     // [2 slots][whiten_resp_floats(n_ch)]
     float* logit = nullptr;    // [cap_logit], absolute logit logit_base at 0
@@ -66,14 +72,13 @@ struct af_server {
     int device = 0;
     hipStream_t stream = nullptr;
     int n_ch = 2, window = 3072, M = 1024, F = 2049, RF = 4097;
+    int64_t seg_step = 2048, n_avg = 63, hop_seg = 8;   // Welch segment grid
     int64_t n0 = 0, block = 2048;
     int64_t cap_raw = 0, cap_w = 0, cap_logit = 0, tick_cap = 0, max_tick_windows = 0;
     size_t stream_bytes = 0, shared_bytes = 0;
     // shared device buffers
     float* white = nullptr;        // [n_ch][max_streams * cap_w]
     int64_t ld_white = 0;
-    void* pgram_ws = nullptr;
-    size_t pgram_bytes = 0;
     void* score_ws = nullptr;
     size_t score_bytes = 0;
     int64_t* d_table = nullptr;
@@ -99,6 +104,7 @@ namespace {
 
 void free_stream(Stream& st) {
     if (st.raw) (void)hipFree(st.raw);
+    if (st.pg_ring) (void)hipFree(st.pg_ring);
     if (st.psd) (void)hipFree(st.psd);
     if (st.resp) (void)hipFree(st.resp);
     if (st.logit) (void)hipFree(st.logit);
@@ -109,7 +115,6 @@ void free_server(af_server* s) {
     if (!s) return;
     for (Stream& st : s->streams) free_stream(st);
     if (s->white) (void)hipFree(s->white);
-    if (s->pgram_ws) (void)hipFree(s->pgram_ws);
     if (s->score_ws) (void)hipFree(s->score_ws);
     if (s->d_table) (void)hipFree(s->d_table);
     if (s->d_logits) (void)hipFree(s->d_logits);
@@ -139,18 +144,30 @@ af_status compact(af_server* s, void* buf, int64_t ld, int64_t from, int64_t to,
     return AF_OK;
 }
 
-// Compute PSD and whitening response of hop h into slot h & 1.
+// Compute PSD and whitening response of hop h into slot h & 1: the
+// periodograms of the background's segments not taken yet go to the ring,
+// then the ring is averaged.
 af_status build_hop(af_server* s, Stream& st, int64_t h) {
     const af_server_config& c = s->cfg;
-    const int64_t start = h * c.psd_hop - st.raw_base;
-    if (start < 0 || start + c.psd_len > st.raw_count - st.raw_base) {
-        set_error("internal error: PSD background of hop %lld is not in the raw buffer", (long long)h);
-        return AF_EINVAL;
+    const int64_t first = h * s->hop_seg, end = first + s->n_avg;   // segments of hop h's background
+    if (st.seg_done < first) st.seg_done = first;
+    while (st.seg_done < end) {
+        const int64_t slot = st.seg_done % s->n_avg;
+        const int64_t run = std::min(end - st.seg_done, s->n_avg - slot);
+        const int64_t start = st.seg_done * s->seg_step - st.raw_base;
+        if (start < 0 || start + (run - 1) * s->seg_step + c.nperseg > st.raw_count - st.raw_base) {
+            set_error("internal error: PSD segments of hop %lld are not in the raw buffer", (long long)h);
+            return AF_EINVAL;
+        }
+        af_status r = welch_pgrams(st.raw + start, s->n_ch, s->cap_raw, c.prescale, c.nperseg, s->seg_step, run,
+                                   st.pg_ring + (size_t)slot * s->n_ch * s->F, s->stream);
+        if (r != AF_OK) return r;
+        st.seg_done += run;
     }
     double* psd = st.psd + (size_t)(h & 1) * s->n_ch * s->F;
     float* resp = st.resp + (size_t)(h & 1) * whiten_resp_floats(s->n_ch);
-    af_status r = af_psd_estimate(st.raw + start, AF_IN_F64, s->n_ch, c.psd_len, s->cap_raw, c.fs, c.prescale,
-                                  c.nperseg, c.noverlap, c.psd_len, 0, 1, psd, s->pgram_ws, s->pgram_bytes, s->stream);
+    af_status r = welch_ring_average(st.pg_ring, s->n_ch, c.nperseg, s->n_avg, first % s->n_avg, s->n_avg, c.fs, psd,
+                                     s->stream);
     if (r != AF_OK) return r;
     return whiten_build_response(psd, s->n_ch, 1, c.nperseg, c.fs, c.highpass, s->M, resp, s->stream);
 }
@@ -208,6 +225,9 @@ extern "C" af_status af_server_create(const af_net* net, const af_server_config*
     s->F = (int)(c.nperseg / 2 + 1);
     s->RF = 8192 / 2 + 1;
     s->n0 = c.psd_len + M;
+    s->seg_step = c.nperseg - c.noverlap;
+    s->n_avg = (c.psd_len - c.nperseg) / s->seg_step + 1;
+    s->hop_seg = c.psd_hop / s->seg_step;
     s->block = c.block;
     s->tick_cap = c.max_tick;
     s->cap_raw = c.psd_len + c.psd_hop + 2 * M + 2 * c.block + c.max_tick + c.max_chunk;
@@ -215,14 +235,13 @@ extern "C" af_status af_server_create(const af_net* net, const af_server_config*
     s->max_tick_windows = (c.max_tick + c.max_chunk + c.block) / c.stride + 2;
     s->cap_logit = c.integrate_width + s->max_tick_windows + 16;
     s->ld_white = c.max_streams * s->cap_w;
-    s->stream_bytes = (size_t)s->n_ch * s->cap_raw * 8 + (size_t)2 * s->n_ch * s->F * 8 +
+    s->stream_bytes = (size_t)s->n_ch * s->cap_raw * 8 + (size_t)(2 + s->n_avg) * s->n_ch * s->F * 8 +
                       (size_t)2 * whiten_resp_floats(s->n_ch) * 4 + (size_t)s->cap_logit * 4;
     const int64_t max_windows = c.max_streams * s->max_tick_windows;
-    s->pgram_bytes = af_psd_workspace_bytes(s->n_ch, c.nperseg, c.noverlap, c.psd_len, 0, 1);
     s->score_bytes = af_timeslide_workspace_bytes(net, 1, 1, std::min<int64_t>(c.score_batch, max_windows));
     s->tmp_bytes = std::max<size_t>((size_t)s->cap_raw * 8, (size_t)s->cap_w * 4);
     s->stage_elems = (size_t)c.max_streams * s->n_ch * (c.max_tick + c.max_chunk);
-    s->shared_bytes = (size_t)s->n_ch * s->ld_white * 4 + s->pgram_bytes + s->score_bytes +
+    s->shared_bytes = (size_t)s->n_ch * s->ld_white * 4 + s->score_bytes +
                       (size_t)c.max_streams * 4 * 8 + (size_t)2 * max_windows * 4 + s->tmp_bytes;
     if (s->shared_bytes > c.hbm_budget) {
         free_server(s);
@@ -236,7 +255,7 @@ extern "C" af_status af_server_create(const af_net* net, const af_server_config*
     if (cur != s->device) { free_server(s); set_error("current device differs from the net's"); return AF_EINVAL; }
     if (hipStreamCreateWithFlags(&s->stream, hipStreamNonBlocking) != hipSuccess ||
         hipMalloc((void**)&s->white, (size_t)s->n_ch * s->ld_white * 4) != hipSuccess ||
-        hipMalloc(&s->pgram_ws, s->pgram_bytes) != hipSuccess || hipMalloc(&s->score_ws, s->score_bytes) != hipSuccess ||
+        hipMalloc(&s->score_ws, s->score_bytes) != hipSuccess ||
         hipMalloc((void**)&s->d_table, (size_t)c.max_streams * 4 * 8) != hipSuccess ||
         hipMalloc((void**)&s->d_logits, (size_t)max_windows * 4) != hipSuccess ||
         hipMalloc((void**)&s->d_integ, (size_t)max_windows * 4) != hipSuccess ||
@@ -291,6 +310,7 @@ extern "C" af_status af_server_admit(af_server* s, int64_t* id) {
     Stream& st = s->streams[slot];
     st = Stream();
     if (hipMalloc((void**)&st.raw, (size_t)s->n_ch * s->cap_raw * 8) != hipSuccess ||
+        hipMalloc((void**)&st.pg_ring, (size_t)s->n_avg * s->n_ch * s->F * 8) != hipSuccess ||
         hipMalloc((void**)&st.psd, (size_t)2 * s->n_ch * s->F * 8) != hipSuccess ||
         hipMalloc((void**)&st.resp, (size_t)2 * whiten_resp_floats(s->n_ch) * 4) != hipSuccess ||
         hipMalloc((void**)&st.logit, (size_t)s->cap_logit * 4) != hipSuccess) {
@@ -375,9 +395,11 @@ extern "C" af_status af_server_tick(af_server* s, int64_t* n_windows) {
                 // and what the next PSD to build needs (hop psd_done reads its
                 // background from psd_done*psd_hop, which lies psd_len - psd_hop
                 // before its first block's context)
+                // the next block's context, and the raw data of the next
+                // periodogram to take
                 const int64_t b = st.white_count / s->block;
                 int64_t keep = s->n0 + b * s->block - s->M;
-                keep = std::min<int64_t>(keep, st.psd_done * c.psd_hop);
+                keep = std::min<int64_t>(keep, std::max(st.seg_done, st.psd_done * s->hop_seg) * s->seg_step);
                 keep = std::min(keep, st.raw_count);
                 af_status r = compact(s, st.raw, s->cap_raw, keep - st.raw_base, st.raw_count - st.raw_base, 8);
                 if (r != AF_OK) return r;

@@ -108,11 +108,14 @@ def run_realtime(server, data, seconds, fs=2048, chunk_s=1.0, prefill_s=66.0, se
     data: list of [n_ch, n] float64 arrays, one per stream (already admitted
     streams 0..S-1).  Each stream is first pre-filled with `prefill_s` seconds
     (pushed and ticked at once) so that its PSD background and first windows
-    exist; latency statistics are reset after the pre-fill.  Then for
-    `seconds` of wall time each stream's next chunk arrives after an
-    exponential gap of mean chunk_s; the loop pushes chunks as their arrival
-    times pass and runs a tick whenever anything is pending.
+    exist; latency statistics are reset after the pre-fill.  Then, for
+    `seconds` of wall time, a producer thread pushes each stream's next chunk
+    at its arrival time (exponential gaps of mean chunk_s), also while a tick
+    runs, and this thread ticks whenever chunks are pending.  The server
+    stamps a chunk when it is pushed, i.e. at its arrival, so the latency
+    includes any wait behind a tick that was already running.
     """
+    import threading
     rng = np.random.default_rng(seed)
     S = len(data)
     n_chunk = int(chunk_s * fs)
@@ -129,31 +132,52 @@ def run_realtime(server, data, seconds, fs=2048, chunk_s=1.0, prefill_s=66.0, se
             server.poll(i)
     server.stats(reset=True)
     t0 = time.perf_counter()
-    nxt = [t0 + rng.exponential(chunk_s) for _ in range(S)]
+    arrivals = []            # (time, stream) in arrival order
+    for i in range(S):
+        t = t0 + rng.exponential(chunk_s)
+        k = pos[i]
+        while t < t0 + seconds and k + n_chunk <= data[i].shape[1]:
+            arrivals.append((t, i, k))
+            k += n_chunk
+            t += rng.exponential(chunk_s)
+    arrivals.sort()
+    pending = threading.Semaphore(0)
+    stop = threading.Event()
+
+    def producer():
+        for t, i, k in arrivals:
+            wait = t - time.perf_counter()
+            if wait > 0:
+                time.sleep(wait)
+            server.push(i, data[i][:, k:k + n_chunk])
+            pending.release()
+        stop.set()
+
+    th = threading.Thread(target=producer, daemon=True)
+    th.start()
     ticks = 0
     last_log = t0
     while True:
-        now = time.perf_counter()
-        if now - t0 > seconds:
-            break
-        pushed = 0
+        if not pending.acquire(timeout=0.05):
+            if stop.is_set():
+                break
+            continue
+        while pending.acquire(blocking=False):   # every chunk pushed so far joins this tick
+            pass
+        server.tick()
+        ticks += 1
         for i in range(S):
-            while nxt[i] <= now and pos[i] + n_chunk <= data[i].shape[1]:
-                server.push(i, data[i][:, pos[i]:pos[i] + n_chunk])
-                pos[i] += n_chunk
-                nxt[i] += rng.exponential(chunk_s)
-                pushed += 1
-        if pushed:
-            server.tick()
-            ticks += 1
-            for i in range(S):
-                server.poll(i)
-        else:
-            time.sleep(max(0.0, min(min(nxt) - time.perf_counter(), 0.002)))
+            server.poll(i)
+        now = time.perf_counter()
         if log and now - last_log > 10:
             log(f"stream run: {now - t0:.0f} s, {ticks} ticks")
             last_log = now
+    th.join()
+    server.tick()
+    for i in range(S):
+        server.poll(i)
     elapsed = time.perf_counter() - t0
     st = server.stats()
-    st.update({"streams": S, "seconds": elapsed, "ticks": ticks, "windows_per_s": st["windows"] / elapsed})
+    st.update({"streams": S, "seconds": elapsed, "ticks": ticks, "windows_per_s": st["windows"] / elapsed,
+               "latency_from": "chunk arrival (pushed by a producer thread at its scheduled time)"})
     return st

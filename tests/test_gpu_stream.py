@@ -122,3 +122,59 @@ def test_budget_admission_and_release():
     assert c == a
     with pytest.raises(P.AframeError, match="EINVAL"):
         srv.push(b, np.zeros((2, 10 ** 6)))          # longer than max_chunk
+
+
+def test_pushes_from_another_thread_during_ticks():
+    # a producer thread pushes chunks of three streams at random moments while
+    # this thread ticks and polls (chunks that arrive while a tick runs join a
+    # later tick); every stream's results equal its run alone, bit for bit
+    P = need_gpu()
+    import threading
+    import time
+    from paper_2403_18661_amd.stream import Collector, Server
+    banner("stream pushes from a second thread during ticks")
+    params = make_params(TINY_ARCH, seed=37)
+    net = P.Net(TINY_ARCH, params, "bf16")
+    xs = [coloured_noise(FS * 76, seed=60 + k) for k in range(3)]
+    srv = Server(net, max_streams=4, hbm_budget=4 << 30)
+    alone = []
+    for x in xs:
+        a = srv.admit()
+        alone.append(run_stream(srv, {a: x}, lambda r: FS, np.random.default_rng(5))[a])
+        srv.release(a)
+    ids = [srv.admit() for _ in range(3)]
+    done = threading.Event()
+
+    def producer():
+        rng = np.random.default_rng(9)
+        pos = [0, 0, 0]
+        while any(pos[k] < xs[k].shape[1] for k in range(3)):
+            k = int(rng.integers(3))
+            if pos[k] >= xs[k].shape[1]:
+                continue
+            n = int(rng.integers(500, 4000))
+            srv.push(ids[k], xs[k][:, pos[k]:pos[k] + n])
+            pos[k] += n
+            time.sleep(float(rng.uniform(0, 0.002)))
+        done.set()
+
+    th = threading.Thread(target=producer)
+    col = Collector()
+    th.start()
+    ticks = 0
+    while not done.is_set():
+        srv.tick()
+        ticks += 1
+        for sid in ids:
+            col.take(srv, sid)
+    th.join()
+    for _ in range(40):     # drain what is still pending (a tick takes at most max_tick per stream)
+        srv.tick()
+    for sid in ids:
+        col.take(srv, sid)
+    assert ticks > 10
+    for k, sid in enumerate(ids):
+        lg, ig = col.arrays(sid)
+        assert len(lg) == len(alone[k][0]) > 50
+        np.testing.assert_array_equal(lg, alone[k][0])
+        np.testing.assert_array_equal(ig, alone[k][1])
