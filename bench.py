@@ -29,11 +29,10 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def cpu_baseline(x, params, arch, n_windows=1536):
-    """The FP64 oracle on the first `n_windows` windows of the same workload:
-    Welch PSD of their 64 s background, whitening filter, whitening of their
-    span, network forward, integration."""
-    import threadpoolctl
+def _oracle_path(x, params, arch, n_windows):
+    """Seconds the FP64 oracle takes for the first `n_windows` windows of the
+    hour workload end to end: Welch PSD of their 64 s background, whitening
+    filter, direct-sum whitening of their span, network forward, integration."""
     import oracle
     fs, M, psd_len, stride, win = 2048.0, 1024, 131072, 128, 3072
     t0 = time.perf_counter()
@@ -43,12 +42,39 @@ def cpu_baseline(x, params, arch, n_windows=1536):
     w = oracle.unfold_windows(y, win, stride)
     logits = oracle.net_forward(params, arch, w)
     oracle.integrate(logits, 16)
-    dt = time.perf_counter() - t0
+    return time.perf_counter() - t0, n_out
+
+
+def host_description():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "cpu_model": model}
+
+
+def cpu_baseline(x, params, arch, n_windows=1536, n_windows_1core=128):
+    """The FP64 oracle timed on the host's cores (its BLAS threads: all the
+    cores it finds) and on one core, each on a bounded sample of the same
+    workload."""
+    import threadpoolctl
+    dt, n_out = _oracle_path(x, params, arch, n_windows)
     threads = max([p.get("num_threads", 1) for p in threadpoolctl.threadpool_info()] + [1])
+    with threadpoolctl.threadpool_limits(1):
+        dt1, n_out1 = _oracle_path(x, params, arch, n_windows_1core)
     return {"value": n_windows / dt, "unit": "windows/s", "cores": int(threads), "kind": "oracle",
             "sample": f"first {n_windows} windows of the same 1 h workload end to end (Welch PSD of their 64 s "
                       f"background, FIR, direct-sum whitening of {n_out} samples, FP64 ResNet forward, "
-                      f"integration); {dt:.1f} s on the host"}
+                      f"integration); {dt:.1f} s on the host",
+            "single_core": {"value": n_windows_1core / dt1, "unit": "windows/s", "cores": 1,
+                            "sample": f"first {n_windows_1core} windows, the same steps ({n_out1} samples "
+                                      f"whitened); {dt1:.1f} s"},
+            "host": host_description()}
 
 
 def events_leg(P, plan, seg_len, n_slides, window, fs, log):
@@ -325,6 +351,63 @@ def gn_leg(args, P, log, xd):
     return out
 
 
+def whiten_leg(args, P, log):
+    """Whitening of one long input: 24 h of two-detector coloured noise (FP64
+    strain, 176.9M samples per detector, in 24 independently coloured hours),
+    rolling 64 s PSD every 8 s, 1 s FIR, 32 Hz high-pass; the block kernel
+    (af_whiten_apply) timed on its stream with HIP events."""
+    import torch
+    from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from synth import TINY_ARCH, make_params
+    from synth.noise import coloured_noise
+    fs = 2048
+    t0 = time.perf_counter()
+    x = np.concatenate([coloured_noise(3600 * fs, seed=7000 + h) for h in range(24)], axis=1)
+    xd = torch.from_numpy(x).cuda()
+    del x
+    net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=0), "bf16")   # only sizes the path's buffers
+    path = OfflinePath(net, xd.shape[1], PathConfig(psd_len=64 * fs), batch=1)
+    log(f"whiten 24 h: input ready ({xd.shape[1]} samples per detector, {path.n_psd} PSD hops) in "
+        f"{time.perf_counter() - t0:.1f} s")
+    stream = torch.cuda.current_stream()
+    path.psd_stage(xd)
+    path.response_stage()
+    path.apply_stage(xd)
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = max(args.steps, 3)
+    ev[0].record(stream)
+    for _ in range(reps):
+        path.psd_stage(xd)
+    ev[1].record(stream)
+    for _ in range(reps):
+        path.response_stage()
+    ev[2].record(stream)
+    for _ in range(reps):
+        path.apply_stage(xd)
+    ev[3].record(stream)
+    ev[3].synchronize()
+    ms = [ev[i].elapsed_time(ev[i + 1]) / reps for i in range(3)]
+    M = fs // 2
+    n_ch = xd.shape[0]
+    # algorithmic bytes: the FP64 input span the outputs need, the FP32 output
+    nbytes = n_ch * ((path.n_out + 2 * M) * 8 + path.n_out * 4)
+    gbs = nbytes / (ms[2] * 1e-3) * 1e-9
+    from paper_2403_18661_amd.profsum import read_traffic
+    pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                    "whitening_24h_kernels.txt"))
+    res = {"hours": 24, "samples_per_detector": int(xd.shape[1]), "outputs_per_detector": int(path.n_out),
+           "psd_hops": int(path.n_psd), "psd_ms": ms[0], "filters_ms": ms[1], "apply_ms": ms[2],
+           "bytes_algorithmic": nbytes, "roofline": {"bound": "hbm", "kernel": "whiten_block_kernel (af_whiten_apply)",
+                                                     "achieved": gbs, "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                                     "frac": gbs / PEAK_HBM_GBS,
+                                                     "traffic": pmc.get("whiten", {}).get("traffic")}}
+    log(f"whiten 24 h: apply {ms[2]:.2f} ms ({gbs:.0f} GB/s algorithmic), PSD {ms[0]:.2f} ms, filters {ms[1]:.2f} ms")
+    del path, xd
+    torch.cuda.empty_cache()
+    return res
+
+
 def stream_leg(args, P, log):
     """Streaming server: S independent two-detector streams, 1 s chunks with
     exponential inter-arrival (mean 1 s), rolling 64 s PSD every 8 s, windows
@@ -369,6 +452,9 @@ def main():
     ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--no-inject", action="store_true")
     ap.add_argument("--no-gn", action="store_true")
+    ap.add_argument("--no-whiten24", action="store_true")
+    ap.add_argument("--whiten-only", action="store_true",
+                    help="run only the 24 h whitening leg (e.g. to profile its kernel) and print its JSON")
     ap.add_argument("--timeslide-only", action="store_true",
                     help="run only the timeslide leg (e.g. to profile its kernel) and print its JSON")
     ap.add_argument("--streams", default="1,16,64")
@@ -399,6 +485,9 @@ def main():
         del src, dst
     if args.timeslide_only:
         print(json.dumps({"timeslide": timeslide_leg(args, P, log)}), flush=True)
+        return
+    if args.whiten_only:
+        print(json.dumps({"whiten_24h": whiten_leg(args, P, log)}), flush=True)
         return
     log("generating 1 h workload")
     x, inj = hour_strain(seed=0, n_windows=args.windows)
@@ -517,14 +606,23 @@ def main():
                      "frac": h["conv"]["frac"], "traffic": pmc.get(head, {}).get("traffic"),
                      "avg_launch_ms": h["conv"]["ms_per_step"] / max(n_launch, 1),
                      "launches_per_step": n_launch},
-        "whiten_roofline": {"bound": "hbm", "kernel": "whiten_block_kernel (af_whiten_apply)",
-                            "achieved": h["whiten_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
-                            "frac": h["whiten_gbs"] / PEAK_HBM_GBS, "traffic": pmc.get("whiten", {}).get("traffic"),
-                            "note": "bound by FP32 VALU work (packed FP32 instructions are disabled), not by HBM"},
+        "whiten_roofline_hour": {"bound": "hbm", "kernel": "whiten_block_kernel (af_whiten_apply)",
+                                 "achieved": h["whiten_gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                                 "frac": h["whiten_gbs"] / PEAK_HBM_GBS,
+                                 "traffic": pmc.get("whiten", {}).get("traffic"),
+                                 "note": "the 1 h input: 1350 blocks, a partial last round on the device"},
         "precisions": precisions,
         "lowp_at_tau_0.99": lowp,
         "stages_ms": h["stages_ms"],
     }
+    if not args.no_whiten24:
+        out["whiten_24h"] = whiten_leg(args, P, log)
+        out["whiten_roofline"] = dict(out["whiten_24h"]["roofline"],
+                                      workload="24 h, 2 detectors, FP64 strain in, FP32 out",
+                                      note="VALU-issue bound: the FFT arithmetic needs more VALU time than "
+                                           "the bytes need HBM time (see profiles/whitening_24h_kernels.txt)")
+    else:
+        out["whiten_roofline"] = out["whiten_roofline_hour"]
     if not args.no_timeslide:
         out["timeslide"] = timeslide_leg(args, P, log)
     if not args.no_rates:

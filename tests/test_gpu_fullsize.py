@@ -1,7 +1,8 @@
 """GPU parity at full size: the 1 h workload in the benchmark's launch
 configuration, checked on sampled outputs that the FP64 oracle recomputes one
 by one (PSD of sampled hops, whitened samples of sampled windows, logits of
-those windows, one integrated value)."""
+those windows in FP32 and in every reduced-precision mode at the 8192-window
+batch, one integrated value)."""
 import numpy as np
 import pytest
 import torch
@@ -31,8 +32,13 @@ def hour_run():
             "logits": path.logits.cpu().numpy(), "integ": path.integrated.cpu().numpy(), "n_windows": path.n_windows}
 
 
+_ORACLE = {}
+
+
 def oracle_window(x, params, k):
     """Oracle whitened span and logit of window k of the hour workload."""
+    if k in _ORACLE:
+        return _ORACLE[k]
     n0 = PSD_LEN + M
     lo, hi = k * STRIDE, k * STRIDE + WIN
     y = np.empty((2, WIN))
@@ -42,7 +48,8 @@ def oracle_window(x, params, k):
         taps = oracle.whitening_fir(psd, FS)
         for c in range(2):
             y[c, a - lo:b - lo] = oracle.whiten_at(x[c], taps[c], np.arange(n0 + a, n0 + b), FS)
-    return y, oracle.net_forward(params, RESNET_ARCH, y[None])[0]
+    _ORACLE[k] = (y, oracle.net_forward(params, RESNET_ARCH, y[None])[0])
+    return _ORACLE[k]
 
 
 def test_counts(hour_run):
@@ -72,3 +79,33 @@ def test_sampled_integrated(hour_run):
     i = 31000
     refs = [oracle_window(hour_run["x"], hour_run["params"], k)[1] for k in range(i, i + 16)]
     assert abs(hour_run["integ"][i] - oracle.integrate(np.array(refs), 16)[0]) < 1e-3
+
+
+LOWP_TOL = {"bf16": 3e-2, "bf16f": 3e-2, "fp8": 1e-1}
+
+
+@pytest.fixture(scope="module")
+def lowp_logits(hour_run):
+    """Logits of all 57,600 windows in each reduced-precision mode, scored in
+    the benchmark's configuration (batch 8192; the FP8 net bias-corrected on
+    64 windows of separate noise, as the benchmark does)."""
+    P = need_gpu()
+    y = torch.from_numpy(hour_run["y"]).cuda()
+    out = {}
+    for prec in LOWP_TOL:
+        banner(f"full-size hour workload, {prec}")
+        net = P.Net(RESNET_ARCH, hour_run["params"], prec)
+        if prec == "fp8":
+            c = np.random.default_rng(99).standard_normal((2, 3072 + 1000 * 63)).astype(np.float32)
+            net.calibrate(torch.from_numpy(c).cuda(), 1000)
+        out[prec] = net.score_windows(y, STRIDE, hour_run["n_windows"], batch=8192).cpu().numpy()
+    return out
+
+
+@pytest.mark.parametrize("prec", list(LOWP_TOL))
+@pytest.mark.parametrize("k", [0, 127, 20000, 45311, 57599])
+def test_sampled_windows_reduced_precision(hour_run, lowp_logits, prec, k):
+    _, logit_ref = oracle_window(hour_run["x"], hour_run["params"], k)
+    err = abs(lowp_logits[prec][k] - logit_ref)
+    print(f"{prec} window {k}: |dlogit| {err:.3e}")
+    assert err < LOWP_TOL[prec]
