@@ -200,8 +200,10 @@ af_status af_net_create(const af_net_desc* desc, const double* params, int64_t n
  * same places as the BatchNorms of af_net_create's network (stem, each conv of
  * a block, each projection).  params (host, float64): per conv, weight
  * [C_out][C_in][k] then gamma [C_out], beta [C_out]; then fc weight [C_last]
- * and fc bias [1].  desc->kernel must be 3; stem_ch and every width a power of
- * two in [16, 256] divisible by groups; precision AF_F32, or AF_BF16_F32ACT
+ * and fc bias [1].  desc->kernel must be 3; stem_ch a power of two in
+ * [16, 256] and every width a power of two in [16, 1024], each divisible by
+ * groups (the standard ResNet34 widths 64/128/256/512 included); precision
+ * AF_F32, or AF_BF16_F32ACT
  * (BF16 conv operands, FP32 activations and GroupNorm); in_ch must be 2.
  * The handle works with af_score_windows, the timeslide entry points, the
  * streaming server, the autotuner and the profile; statistics are taken per

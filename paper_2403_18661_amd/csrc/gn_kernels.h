@@ -150,7 +150,7 @@ struct GnArgs {
     float* out;           // [B][L_out][C]; may alias in or res when pool == 0
     const float* gamma;   // [C]
     const float* beta;    // [C]
-    int L, C, G;          // C a power of two in [16, 256], G divides C
+    int L, C, G;          // C a power of two in [16, 1024], G divides C
     int relu;             // ReLU after the (residual) add
     int pool;             // max-pool k3 s2 p1 after the ReLU (relu must be set)
 };
@@ -158,7 +158,8 @@ struct GnArgs {
 // GroupNorm of one window per workgroup (256 threads).  Pass 1: per-channel
 // sums and sums of squares in FP64 (1024 is a multiple of C, so a thread's
 // four channels stay fixed as it strides through the window's float4s),
-// reduced per group in a fixed order: mean and biased variance.  Pass 2:
+// reduced per group in a fixed order: mean and biased variance, for channels
+// tid, tid + 256, ... .  Pass 2:
 // v * scale_c + shift_c with scale_c = gamma_c / sqrt(var_g + eps),
 // shift_c = beta_c - mean_g scale_c, then residual add, ReLU, pool.  Each
 // element of `out` is written by the thread that read it in pass 2, and pass 1
@@ -166,7 +167,7 @@ struct GnArgs {
 __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
     constexpr int U = 8;   // float4 loads in flight per thread
     __shared__ double part[2][1024];
-    __shared__ float sc[256], sh[256];
+    __shared__ float sc[1024], sh[1024];
     const int tid = threadIdx.x, C = a.C, L = a.L;
     const size_t b = blockIdx.x;
     const float4* in = (const float4*)(a.in + b * L * C);
@@ -194,8 +195,8 @@ __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
     }
     __syncthreads();
     // slot p of part holds channel p % C; channel c of group g = c / (C / G)
-    if (tid < C) {
-        const int cpg = C / a.G, g = tid / cpg;
+    for (int ch = tid; ch < C; ch += 256) {
+        const int cpg = C / a.G, g = ch / cpg;
         double gs = 0.0, gq = 0.0;
         for (int c = g * cpg; c < (g + 1) * cpg; ++c)
             for (int p = c; p < 1024; p += C) {
@@ -205,9 +206,9 @@ __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
         const double n = (double)cpg * L;
         const double mean = gs / n;
         const double var = fmax(gq / n - mean * mean, 0.0);
-        const double scale = (double)a.gamma[tid] / sqrt(var + 1e-5);
-        sc[tid] = (float)scale;
-        sh[tid] = (float)((double)a.beta[tid] - mean * scale);
+        const double scale = (double)a.gamma[ch] / sqrt(var + 1e-5);
+        sc[ch] = (float)scale;
+        sh[ch] = (float)((double)a.beta[ch] - mean * scale);
     }
     __syncthreads();
     const int c0 = (4 * tid) % C;
@@ -259,8 +260,8 @@ __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
 
 // GroupNorm of one window per workgroup with the window held in registers
 // (no pool): NT threads, up to R float4s each, so a window of up to 4 NT R
-// elements is read from HBM once instead of twice.  Each thread's channels
-// are fixed (C divides 4 NT); its sums and sums of squares per channel (FP32,
+// elements is read from HBM once instead of twice, for C <= 256.  Each
+// thread's channels are fixed (C divides 4 NT); its sums and sums of squares per channel (FP32,
 // R terms each) are reduced in FP64 across the lanes that share channels (lane xor C/4 .. 32), then
 // across the NT / 64 waves and per group in a fixed order.  Then as gn_kernel:
 // scale, shift, residual, ReLU; every element is read and written by one

@@ -381,8 +381,8 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
                      "GroupNorm nets run in AF_F32 or AF_BF16_F32ACT");
         AF_CHECK_ARG(groups <= 256 && d->stem_ch % groups == 0, "groups must divide stem_ch");
         for (int st = 0; st < d->n_stages && st < 8; ++st)
-            AF_CHECK_ARG(d->widths[st] % groups == 0 && d->widths[st] >= 16 && 256 % d->widths[st] == 0,
-                         "GroupNorm widths must be powers of two in [16, 256] divisible by groups");
+            AF_CHECK_ARG(d->widths[st] % groups == 0 && d->widths[st] >= 16 && 1024 % d->widths[st] == 0,
+                         "GroupNorm widths must be powers of two in [16, 1024] divisible by groups");
     } else {
         AF_CHECK_ARG(d->kernel == 7, "only kernel 7 is implemented");
     }
@@ -735,7 +735,7 @@ void launch_gn(const af_net* net, const void* in, const void* res, void* out, si
     g.beta = g.gamma + C;
     g.L = L; g.C = C; g.G = net->gn_groups; g.relu = relu; g.pool = pool;
     constexpr int NT = 1024, R = 6;   // threads and float4s per thread of the register-resident form
-    if (!pool && (int64_t)L * C <= 4LL * NT * R)
+    if (!pool && C <= 256 && (int64_t)L * C <= 4LL * NT * R)
         hipLaunchKernelGGL((gn_reg_kernel<NT, R>), dim3((unsigned)nb), dim3(NT), 0, s, g);
     else
         hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);

@@ -11,9 +11,9 @@ part of the input recipe: neither the oracle nor the library calls it.
 from .noise import analytic_psd, coloured_noise
 from .chirps import newtonian_chirp, inject_chirps
 from .segments import lognormal_segments
-from .params import NetArch, TINY_ARCH, RESNET_ARCH, GN_ARCH, TINY_GN_ARCH, make_params
+from .params import NetArch, TINY_ARCH, RESNET_ARCH, GN_ARCH, GN_NARROW_ARCH, TINY_GN_ARCH, make_params
 
 __all__ = [
     "analytic_psd", "coloured_noise", "newtonian_chirp", "inject_chirps",
-    "lognormal_segments", "NetArch", "TINY_ARCH", "RESNET_ARCH", "GN_ARCH", "TINY_GN_ARCH", "make_params",
+    "lognormal_segments", "NetArch", "TINY_ARCH", "RESNET_ARCH", "GN_ARCH", "GN_NARROW_ARCH", "TINY_GN_ARCH", "make_params",
 ]

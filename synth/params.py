@@ -53,9 +53,13 @@ TINY_ARCH = NetArch("tiny", in_ch=2, stem_ch=16, kernel=7, stem_stride=1,
                     stem_pool=False, widths=(16,), blocks=(2,))
 RESNET_ARCH = NetArch("resnet", in_ch=2, stem_ch=32, kernel=7, stem_stride=2,
                       stem_pool=True, widths=(32, 64, 128, 256), blocks=(3, 4, 6, 3))
-# the paper's form: GroupNorm, kernel length 3, ResNet34 depth
-GN_ARCH = NetArch("resnet34-gn", in_ch=2, stem_ch=32, kernel=3, stem_stride=2, stem_pool=True,
-                  widths=(32, 64, 128, 256), blocks=(3, 4, 6, 3), norm="gn", groups=8)
+# the paper's form: GroupNorm, kernel length 3, ResNet34 at its standard
+# widths (64-channel stem, stages of 64, 128, 256 and 512 channels)
+GN_ARCH = NetArch("resnet34-gn", in_ch=2, stem_ch=64, kernel=3, stem_stride=2, stem_pool=True,
+                  widths=(64, 128, 256, 512), blocks=(3, 4, 6, 3), norm="gn", groups=8)
+# the same depth at half the widths (the widths of the BatchNorm network)
+GN_NARROW_ARCH = NetArch("resnet34-gn-narrow", in_ch=2, stem_ch=32, kernel=3, stem_stride=2, stem_pool=True,
+                         widths=(32, 64, 128, 256), blocks=(3, 4, 6, 3), norm="gn", groups=8)
 TINY_GN_ARCH = NetArch("tiny-gn", in_ch=2, stem_ch=32, kernel=3, stem_stride=2, stem_pool=True,
                        widths=(32, 64), blocks=(2, 1), window=512, norm="gn", groups=8)
 

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 import oracle
-from synth import GN_ARCH, TINY_GN_ARCH, make_params
+from synth import GN_ARCH, GN_NARROW_ARCH, TINY_GN_ARCH, make_params
 from tests.gpu_util import banner, dev, need_gpu
 
 pytestmark = pytest.mark.gpu
@@ -27,11 +27,17 @@ def oracle_logits(params, arch, y, stride, nw, shifts=None, wrap=0):
 # a 480-sample window gives a 240-row stem, which the one-pass stem kernel does
 # not take (rows per thread block must be even): the two-kernel stem runs
 TINY480_GN_ARCH = dataclasses.replace(TINY_GN_ARCH, name="tiny480-gn", window=480)
+# the widest stages the GroupNorm net takes (1024 channels), on a short window
+WIDE_GN_ARCH = dataclasses.replace(TINY_GN_ARCH, name="wide-gn", stem_ch=64, widths=(64, 1024), blocks=(1, 2))
 
 
 @pytest.mark.parametrize("arch,prec,nw", [(TINY_GN_ARCH, "f32", 37), (TINY_GN_ARCH, "bf16f", 37),
-                                          (TINY480_GN_ARCH, "f32", 9), (GN_ARCH, "f32", 5), (GN_ARCH, "bf16f", 5)],
-                         ids=["tiny-f32", "tiny-bf16f", "tiny480-f32", "resnet34-f32", "resnet34-bf16f"])
+                                          (TINY480_GN_ARCH, "f32", 9), (WIDE_GN_ARCH, "f32", 11),
+                                          (WIDE_GN_ARCH, "bf16f", 11),
+                                          (GN_NARROW_ARCH, "f32", 5), (GN_NARROW_ARCH, "bf16f", 5),
+                                          (GN_ARCH, "f32", 5), (GN_ARCH, "bf16f", 5)],
+                         ids=["tiny-f32", "tiny-bf16f", "tiny480-f32", "wide-f32", "wide-bf16f",
+                              "resnet34-narrow-f32", "resnet34-narrow-bf16f", "resnet34-f32", "resnet34-bf16f"])
 def test_gn_net_matches_oracle(arch, prec, nw):
     P = need_gpu()
     banner(f"gn net {arch.name} {prec} nw={nw}")

@@ -5,7 +5,7 @@ import torch
 
 import oracle
 from oracle.net_gn import group_norm
-from synth import GN_ARCH, TINY_GN_ARCH, make_params
+from synth import GN_ARCH, GN_NARROW_ARCH, TINY_GN_ARCH, make_params
 
 
 def test_group_norm_matches_brute_force_loops():
@@ -98,7 +98,8 @@ def torch_gn_model(arch, params):
     return run
 
 
-@pytest.mark.parametrize("arch", [TINY_GN_ARCH, GN_ARCH], ids=["tiny-gn", "resnet34-gn"])
+@pytest.mark.parametrize("arch", [TINY_GN_ARCH, GN_NARROW_ARCH, GN_ARCH],
+                         ids=["tiny-gn", "resnet34-gn-narrow", "resnet34-gn"])
 def test_forward_matches_torch_gn_model(arch):
     params = make_params(arch, seed=5)
     x = np.random.default_rng(6).standard_normal((2, arch.in_ch, arch.window))
