@@ -287,20 +287,22 @@ def inject_leg(args, P, log):
 
 
 def gn_bytes(arch, windows):
-    """Algorithmic HBM bytes of the GroupNorm launches over `windows` windows:
-    each reads its conv's FP32 output (and the residual) once and writes its
-    output once.  A 32-channel stem's norm runs inside the stem kernel and is
-    timed with it; a wider stem's reads the raw stem output and writes the
-    pooled one."""
+    """Algorithmic HBM bytes of the GroupNorm launches over `windows` windows.
+    Per conv, the finalize kernel reads the conv's statistics (a sum and a sum
+    of squares per channel and 16-row block) and writes a scale and a shift
+    per channel; per block, the apply kernel reads the second conv's FP32
+    output and the skip once and writes the block output once (the first
+    conv's norm is applied inside the second conv as it loads its input).  A
+    32-channel stem's norm runs inside the stem kernel and is timed with it;
+    a wider stem's reads the raw stem output and writes the pooled one."""
     l_conv = (arch.window + 2 * (arch.kernel // 2) - arch.kernel) // arch.stem_stride + 1
     L = (l_conv - 1) // 2 + 1 if arch.stem_pool else l_conv
     b = 0 if arch.stem_ch == 32 else (l_conv + L) * arch.stem_ch
     for _, _, c_out, stride, proj in arch.block_list():
         lo = (L - 1) // stride + 1
-        b += 2 * lo * c_out                     # conv1: in place
-        if proj:
-            b += 2 * lo * c_out                 # projection: in place
-        b += 3 * lo * c_out                     # conv2: in, residual, out
+        n_conv = 3 if proj else 2
+        b += n_conv * (2 * ((lo + 15) // 16) * c_out + 2 * c_out)   # finalize
+        b += 3 * lo * c_out                                           # apply
         L = lo
     return 4 * b * windows
 

@@ -1,8 +1,12 @@
 // Kernels of the GroupNorm form of the scoring network (GroupNorm in place of
 // BatchNorm, Sec. II).  GroupNorm normalises with statistics of the window
-// being scored, so it cannot be folded into the convolutions: each conv runs
-// as the implicit-GEMM kernel with no bias and no ReLU, and gn_kernel then
-// normalises its output.
+// being scored, so it cannot be folded into the weights: each conv of a block
+// runs as the implicit-GEMM kernel with no bias and no ReLU and writes the
+// statistics of its output as it stores it; gn_finalize_kernel turns them
+// into per-channel scales and shifts; the block's second conv applies the
+// first one's as it stages its input, and gn_apply_kernel ends the block
+// (second norm, the projection's norm on the skip, residual add, ReLU).  The
+// stem's norm runs in the stem kernel or in gn_kernel.
 #pragma once
 
 #include "net_kernels.h"
@@ -48,9 +52,10 @@ __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a) {
 // max-pool whose raw output has a multiple of 64 rows, at most 32 MAXR: raw
 // conv -> GroupNorm -> ReLU -> max-pool k3 s2 p1, with the raw output held in
 // registers.  1024 threads: thread t keeps channel t % 32 of the R = L_conv / 32
-// consecutive rows of row block t / 32.  Statistics as in gn_reg_kernel (lanes
-// l and l xor 32 share a channel).  Pooled row p of a block takes its rows
-// 2p - 1 .. 2p + 1; the first of them for p = 0 is the previous block's last
+// consecutive rows of row block t / 32.  Statistics in FP64: a thread's R values,
+// then across lanes l and l xor 32 (which share a channel), the 16 waves and
+// the group's channels, in a fixed order.  Pooled row p of a block takes its
+// rows 2p - 1 .. 2p + 1; the first of them for p = 0 is the previous block's last
 // row, passed through LDS (row -1 is padding: every candidate is >= 0, so 0
 // stands in for it).
 template <int NCH, int KW, int MAXR>
@@ -258,119 +263,106 @@ __global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
     }
 }
 
-// GroupNorm of one window per workgroup with the window held in registers
-// (no pool): NT threads, up to R float4s each, so a window of up to 4 NT R
-// elements is read from HBM once instead of twice, for C <= 256.  Each
-// thread's channels are fixed (C divides 4 NT); its sums and sums of squares per channel (FP32,
-// R terms each) are reduced in FP64 across the lanes that share channels (lane xor C/4 .. 32), then
-// across the NT / 64 waves and per group in a fixed order.  Then as gn_kernel:
-// scale, shift, residual, ReLU; every element is read and written by one
-// thread, so out may alias in or res.
-template <int NT, int R>
-__global__ void __launch_bounds__(NT) gn_reg_kernel(GnArgs a) {
-    constexpr int NW = NT / 64;
-    __shared__ double part[2][NW][256];
-    __shared__ double chs[2][256];
-    __shared__ float sc[256], sh[256];
-    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6, C = a.C, L = a.L;
+// GroupNorm scale and shift of one window per workgroup (256 threads) from
+// the statistics the conv wrote: per channel, the sums and sums of squares of
+// its nblk 16-row blocks are added in FP64, in block order (split over
+// 256 / C strided parts when C < 256, the parts then added in order), then
+// per group of C / G consecutive channels in channel order: mean, biased
+// variance, scale_c = gamma_c / sqrt(var + eps), shift_c = beta_c -
+// mean scale_c.  aff is [B][2][C] (scales, then shifts).
+__global__ void __launch_bounds__(256) gn_finalize_kernel(const float* stats, int nblk, int L, int C, int G,
+                                                          const float* gamma, const float* beta, float* aff) {
+    __shared__ double part[2][1024];
+    const int tid = threadIdx.x;
     const size_t b = blockIdx.x;
-    const float4* in = (const float4*)(a.in + b * L * C);
-    const int n4 = L * C / 4;
-    float4 v[R];
-#pragma unroll
-    for (int u = 0; u < R; ++u) v[u] = in[min(tid + NT * u, n4 - 1)];
-    // a thread's R values per channel summed in FP32, the rest of the
-    // reduction in FP64
-    float sf[4] = {0.f, 0.f, 0.f, 0.f}, qf[4] = {0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-    for (int u = 0; u < R; ++u) {
-        if (tid + NT * u < n4) {
-            const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                sf[k] += e[k];
-                qf[k] = fmaf(e[k], e[k], qf[k]);
-            }
+    const int per = C < 256 ? 256 / C : 1;
+    const float* st = stats + b * nblk * 2 * C;
+    for (int idx = tid; idx < per * C; idx += 256) {
+        const int c = idx % C, pp = idx / C;
+        double s = 0.0, q = 0.0;
+        for (int k = pp; k < nblk; k += per) {
+            s += (double)st[(size_t)k * 2 * C + c];
+            q += (double)st[(size_t)k * 2 * C + C + c];
         }
-    }
-    double s[4], q[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        s[k] = sf[k];
-        q[k] = qf[k];
-    }
-    // lane l holds channels 4l % C .. +3; lanes l and l xor m (m >= C/4) share them
-    for (int off = C / 4; off < 64; off <<= 1)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            s[k] += __shfl_xor(s[k], off);
-            q[k] += __shfl_xor(q[k], off);
-        }
-    if (lane < C / 4)
-#pragma unroll
-        for (int k = 0; k < 4; ++k) {
-            part[0][wv][4 * lane + k] = s[k];
-            part[1][wv][4 * lane + k] = q[k];
-        }
-    __syncthreads();
-    if (tid < C) {
-        double cs = 0.0, cq = 0.0;
-        for (int w = 0; w < NW; ++w) {
-            cs += part[0][w][tid];
-            cq += part[1][w][tid];
-        }
-        chs[0][tid] = cs;
-        chs[1][tid] = cq;
+        part[0][idx] = s;
+        part[1][idx] = q;
     }
     __syncthreads();
-    if (tid < C) {
-        const int cpg = C / a.G, g = tid / cpg;
+    const int cpg = C / G;
+    for (int c = tid; c < C; c += 256) {
+        const int g = c / cpg;
         double gs = 0.0, gq = 0.0;
-        for (int c = g * cpg; c < (g + 1) * cpg; ++c) {
-            gs += chs[0][c];
-            gq += chs[1][c];
-        }
+        for (int cc = g * cpg; cc < (g + 1) * cpg; ++cc)
+            for (int pp = 0; pp < per; ++pp) {
+                gs += part[0][pp * C + cc];
+                gq += part[1][pp * C + cc];
+            }
         const double n = (double)cpg * L;
         const double mean = gs / n;
         const double var = fmax(gq / n - mean * mean, 0.0);
-        const double scale = (double)a.gamma[tid] / sqrt(var + 1e-5);
-        sc[tid] = (float)scale;
-        sh[tid] = (float)((double)a.beta[tid] - mean * scale);
+        const double scale = (double)gamma[c] / sqrt(var + 1e-5);
+        aff[b * 2 * C + c] = (float)scale;
+        aff[b * 2 * C + C + c] = (float)((double)beta[c] - mean * scale);
+    }
+}
+
+// out = relu(in scale + shift + r), r = res scale_r + shift_r (the residual's
+// own GroupNorm, res_aff non-null) or res (res_aff null), or 0 (res null):
+// the normalisation that ends a residual block.  Workgroup k takes slice
+// k % n_slice of window k / n_slice: it stages the window's scales and shifts
+// in LDS and takes U float4s per thread of the slice.  Each element is read and written by one thread,
+// so out may alias in or res.
+struct GnApplyArgs {
+    const float* in;        // [B][L][C]
+    const float* res;       // [B][L][C] or null
+    float* out;             // [B][L][C]
+    const float* aff;       // [B][2][C]
+    const float* res_aff;   // [B][2][C] or null
+    int LC4, C;             // float4s per window, channels (a multiple of 4, at most 1024)
+    int relu;
+    int n_slice;            // workgroups per window: ceil(LC4 / (256 U))
+};
+template <int U>
+__global__ void __launch_bounds__(256) gn_apply_kernel(GnApplyArgs a) {
+    __shared__ float4 saff[2][256], raff[2][256];
+    const int tid = threadIdx.x, C4 = a.C >> 2;
+    const size_t b = blockIdx.x / a.n_slice;
+    const int slice = (int)(blockIdx.x % a.n_slice);
+    for (int c = tid; c < C4; c += 256) {
+        saff[0][c] = ((const float4*)(a.aff + b * 2 * a.C))[c];
+        saff[1][c] = ((const float4*)(a.aff + b * 2 * a.C + a.C))[c];
+        if (a.res_aff) {
+            raff[0][c] = ((const float4*)(a.res_aff + b * 2 * a.C))[c];
+            raff[1][c] = ((const float4*)(a.res_aff + b * 2 * a.C + a.C))[c];
+        }
     }
     __syncthreads();
-    const int c0 = (4 * tid) % C;
-    const float4 S = make_float4(sc[c0], sc[c0 + 1], sc[c0 + 2], sc[c0 + 3]);
-    const float4 H = make_float4(sh[c0], sh[c0 + 1], sh[c0 + 2], sh[c0 + 3]);
-    float4* out = (float4*)(a.out + b * L * C);
-    if (a.res) {
-        // the residual in groups of RC float4s, to stay within 128 registers
-        constexpr int RC = 4;
-        const float4* res = (const float4*)(a.res + b * L * C);
+    const float4* in = (const float4*)a.in + b * a.LC4;
+    const float4* res = a.res ? (const float4*)a.res + b * a.LC4 : nullptr;
+    float4* out = (float4*)a.out + b * a.LC4;
+    const int i0 = slice * 256 * U + tid;
+    float4 v[U], r[U];
 #pragma unroll
-        for (int u0 = 0; u0 < R; u0 += RC) {
-            float4 r[RC];
-#pragma unroll
-            for (int u = 0; u < RC && u0 + u < R; ++u) r[u] = res[min(tid + NT * (u0 + u), n4 - 1)];
-#pragma unroll
-            for (int u = 0; u < RC && u0 + u < R; ++u) {
-                float4& x = v[u0 + u];
-                x = make_float4(fmaf(x.x, S.x, H.x) + r[u].x, fmaf(x.y, S.y, H.y) + r[u].y,
-                                fmaf(x.z, S.z, H.z) + r[u].z, fmaf(x.w, S.w, H.w) + r[u].w);
-            }
-        }
-    } else {
-#pragma unroll
-        for (int u = 0; u < R; ++u)
-            v[u] = make_float4(fmaf(v[u].x, S.x, H.x), fmaf(v[u].y, S.y, H.y), fmaf(v[u].z, S.z, H.z),
-                               fmaf(v[u].w, S.w, H.w));
+    for (int u = 0; u < U; ++u) {
+        const int i = min(i0 + 256 * u, a.LC4 - 1);
+        v[u] = in[i];
+        r[u] = res ? res[i] : make_float4(0.f, 0.f, 0.f, 0.f);
     }
+    auto fma4 = [](float4 x, float4 m, float4 c) {
+        return make_float4(fmaf(x.x, m.x, c.x), fmaf(x.y, m.y, c.y), fmaf(x.z, m.z, c.z), fmaf(x.w, m.w, c.w));
+    };
 #pragma unroll
-    for (int u = 0; u < R; ++u) {
-        if (tid + NT * u < n4) {
-            float4 y = v[u];
-            if (a.relu) y = make_float4(fmaxf(y.x, 0.f), fmaxf(y.y, 0.f), fmaxf(y.z, 0.f), fmaxf(y.w, 0.f));
-            out[tid + NT * u] = y;
+    for (int u = 0; u < U; ++u) {
+        const int i = i0 + 256 * u;
+        if (i >= a.LC4) break;
+        const int c4 = i % C4;
+        float4 y = fma4(v[u], saff[0][c4], saff[1][c4]);
+        if (res) {
+            const float4 rr = a.res_aff ? fma4(r[u], raff[0][c4], raff[1][c4]) : r[u];
+            y = make_float4(y.x + rr.x, y.y + rr.y, y.z + rr.z, y.w + rr.w);
         }
+        if (a.relu) y = make_float4(fmaxf(y.x, 0.f), fmaxf(y.y, 0.f), fmaxf(y.z, 0.f), fmaxf(y.w, 0.f));
+        out[i] = y;
     }
 }
 

@@ -61,22 +61,22 @@ using Cands = std::vector<ConvCfg>;
 // autotuner (af_net_autotune) may pick another by timing.
 // FP32: 16-channel chunks, single LDS buffer (two workgroups per CU overlap
 // staging with compute).
-template <int KW, int S>
+template <int KW, int S, typename P = PF32>
 Cands cands_f32(int c_out) {
     if (c_out % 128 == 0)
-        return {make_cfg<PF32, KW, S, 2, 2, 3, 4, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, false>(),
-                make_cfg<PF32, KW, S, 2, 2, 2, 4, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
-                make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 0>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
+        return {make_cfg<P, KW, S, 2, 2, 3, 4, 16, 1, false>(), make_cfg<P, KW, S, 2, 2, 6, 2, 16, 2, false>(),
+                make_cfg<P, KW, S, 2, 2, 2, 4, 16, 1, false>(), make_cfg<P, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
+                make_cfg<P, KW, S, 4, 1, 3, 4, 16, 2, 0>(), make_cfg<P, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
     if (c_out == 64)
-        return {make_cfg<PF32, KW, S, 2, 2, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 1, false>(),
-                make_cfg<PF32, KW, S, 2, 2, 2, 2, 16, 1, false>(), make_cfg<PF32, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
-                make_cfg<PF32, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
+        return {make_cfg<P, KW, S, 2, 2, 3, 2, 16, 1, false>(), make_cfg<P, KW, S, 4, 1, 3, 4, 16, 1, false>(),
+                make_cfg<P, KW, S, 2, 2, 2, 2, 16, 1, false>(), make_cfg<P, KW, S, 2, 2, 6, 2, 16, 2, 2>(),
+                make_cfg<P, KW, S, 4, 1, 3, 4, 16, 2, 2>()};
     if constexpr ((KW == 7 || KW == 3) && S == 1) {
         if (c_out == 32)
-            return {make_cfg<PF32, KW, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<PF32, KW, 1, 4, 1, 2, 2, 16, 1, false>(),
-                    make_cfg<PF32, KW, 1, 2, 2, 6, 1, 16, 1, false>()};
-        if (c_out == 16)
-            return {make_cfg<PF32, 7, 1, 4, 1, 4, 1, 16, 1, false>(), make_cfg<PF32, 7, 1, 4, 1, 2, 1, 16, 1, false>()};
+            return {make_cfg<P, KW, 1, 4, 1, 3, 2, 16, 1, false>(), make_cfg<P, KW, 1, 4, 1, 2, 2, 16, 1, false>(),
+                    make_cfg<P, KW, 1, 2, 2, 6, 1, 16, 1, false>()};
+        if (KW == 7 && c_out == 16)
+            return {make_cfg<P, 7, 1, 4, 1, 4, 1, 16, 1, false>(), make_cfg<P, 7, 1, 4, 1, 2, 1, 16, 1, false>()};
     }
     return {};
 }
@@ -135,6 +135,31 @@ Cands cands_shape_lowp(int kw, int s, int c_out) {
     return {};
 }
 
+// Convs of the GroupNorm net (k3, and 1x1 stride-2 projections): every one
+// writes its output's statistics; AFF (a block's second conv) also normalises
+// its input as it stages it.  FP32, or BF16 operands with FP32 activations.
+template <bool AFF>
+Cands gn_conv_candidates(af_precision p, int kw, int s, int c_in, int c_out) {
+    if (p == AF_F32) {
+        using P = PGn<PF32, AFF>;
+        if (c_in % 16 != 0) return {};
+        if (kw == 3 && s == 1) return cands_f32<3, 1, P>(c_out);
+        if constexpr (!AFF) {
+            if (kw == 3 && s == 2) return c_out >= 64 ? cands_f32<3, 2, P>(c_out) : Cands{};
+            if (kw == 1 && s == 2) return c_out >= 64 ? cands_f32<1, 2, P>(c_out) : Cands{};
+        }
+        return {};
+    }
+    if (p != AF_BF16_F32ACT || c_in % 32 != 0) return {};
+    using P = PGn<PBF16F, AFF>;
+    if (kw == 3 && s == 1) return cands_k3<P, 1>(c_out);
+    if constexpr (!AFF) {
+        if (kw == 3 && s == 2) return cands_k3<P, 2>(c_out);
+        if (kw == 1 && s == 2) return c_out >= 64 ? cands_lowp<P, 1, 2, 32>(c_out) : Cands{};
+    }
+    return {};
+}
+
 // role: 1 for the first conv of a residual block (it writes the block's inner
 // activation), 2 for the second (it reads it), 0 for any other conv
 Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int role) {
@@ -143,8 +168,6 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int ro
         if (kw == 7 && s == 1) return cands_f32<7, 1>(c_out);
         if (kw == 7 && s == 2) return c_out >= 64 ? cands_f32<7, 2>(c_out) : Cands{};
         if (kw == 1 && s == 2) return c_out >= 64 ? cands_f32<1, 2>(c_out) : Cands{};
-        if (kw == 3 && s == 1) return cands_f32<3, 1>(c_out);
-        if (kw == 3 && s == 2) return c_out >= 64 ? cands_f32<3, 2>(c_out) : Cands{};
         return {};
     }
     const bool kc32 = c_in % 32 == 0;
@@ -166,7 +189,6 @@ Cands conv_candidates(af_precision p, int kw, int s, int c_in, int c_out, int ro
         }
         if (role == 2 && kw == 7 && s == 1)
             return kc32 ? cands_lowp<PBF16BF, 7, 1, 32>(c_out) : cands_lowp<PBF16BF, 7, 1, 16>(c_out);
-        if (kw == 3) return !kc32 ? Cands{} : s == 1 ? cands_k3<PBF16F, 1>(c_out) : cands_k3<PBF16F, 2>(c_out);
         if (kc32) return cands_shape_lowp<PBF16F, 32>(kw, s, c_out);
         return kw == 7 && s == 1 ? cands_lowp<PBF16F, 7, 1, 16>(c_out) : Cands{};
     }
@@ -244,10 +266,15 @@ struct ConvOp {
     ConvCfg cfg;
     int wpt, tt, tiles_per_win;
     void* d_img = nullptr;         // weight image for cfg (device)
-    // GroupNorm nets: the conv's output buffer is normalised into gn_out (with
-    // gamma, beta at gn_off of the net's table), plus gn_res, then ReLU
+    // GroupNorm nets: gamma, beta of the conv's norm at gn_off of the net's
+    // table; its scales and shifts go to slot gn_aff (0: a block's first conv,
+    // 1: projection, 2: second conv); the second conv stages its input
+    // through slot 0's and then ends the block: its output normalised, plus
+    // the skip gn_res (through slot 1's when the block has a projection),
+    // ReLU, into gn_out
     size_t gn_off = 0;
-    int gn_out = -1, gn_res = -1, gn_relu = 0;
+    int gn_aff = -1;
+    int gn_out = -1, gn_res = -1, gn_res_aff = -1;
 };
 
 // M tiling of a layer for its tile height: several short windows per tile, or
@@ -300,6 +327,9 @@ struct af_net {
     int64_t macs;
     int stem_lconv, stem_lout;
     int64_t act_elems;  // per window, max over layers
+    // GroupNorm nets, per window: conv output statistics ([blocks][2][C], max
+    // over layers) and one slot of scales and shifts ([2][C], max over layers)
+    int64_t gn_stats_elems = 0, gn_aff_elems = 0;
     int n_slots;
     int last_L, last_C;
     float fc_b;
@@ -461,7 +491,11 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
         op.amax_out = n_slots++;
         op.w_off = wfold.size();
         op.b_off = bias.size();
-        op.cands = conv_candidates(prec, kw, s, c_in, c_out, groups ? 0 : out_buf == BR ? 1 : (in_buf == BR ? 2 : 0));
+        if (groups)   // the block's second conv reads BR
+            op.cands = in_buf == BR ? gn_conv_candidates<true>(prec, kw, s, c_in, c_out)
+                                    : gn_conv_candidates<false>(prec, kw, s, c_in, c_out);
+        else
+            op.cands = conv_candidates(prec, kw, s, c_in, c_out, out_buf == BR ? 1 : (in_buf == BR ? 2 : 0));
         op.cand = 0;
         op.cfg = op.cands.empty() ? ConvCfg{} : op.cands[0];
         if (!op.cfg.fn) {
@@ -469,7 +503,7 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
             return false;
         }
         if (!take_conv(c_out, c_in, kw, w, b)) { set_error("params too short"); return false; }
-        if (groups) {   // raw conv; GroupNorm, residual and ReLU follow in gn_kernel
+        if (groups) {   // raw conv; GroupNorm, residual and ReLU are applied later
             op.relu = 0;
             op.res_buf = -1;
             op.gn_off = gn_off;
@@ -481,6 +515,10 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
         net->macs += (int64_t)op.l_out * c_out * c_in * kw;
         net->layer_macs.push_back((int64_t)op.l_out * c_out * c_in * kw);
         net->act_elems = std::max<int64_t>(net->act_elems, (int64_t)op.l_out * c_out);
+        if (groups) {
+            net->gn_stats_elems = std::max<int64_t>(net->gn_stats_elems, (int64_t)(op.l_out + 15) / 16 * 2 * c_out);
+            net->gn_aff_elems = std::max<int64_t>(net->gn_aff_elems, 2 * (int64_t)c_out);
+        }
         net->ops.push_back(op);
         return true;
     };
@@ -504,19 +542,21 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
                 slot_x = net->ops.back().amax_out;
             }
             if (groups) {
-                // buffers: conv1 X -> R, GN(R) -> R, ReLU; with a projection,
-                // proj X -> P, GN(P) -> P, then conv2 R -> X, GN(X) + P -> X,
-                // ReLU; without, conv2 R -> P, GN(P) + X -> X, ReLU
+                // buffers: conv1 X -> R (raw); with a projection, proj X -> P
+                // (raw), then conv2 relu(GN1(R)) -> X (raw), and the block
+                // ends GN2(X) + GNp(P) -> X, ReLU; without, conv2
+                // relu(GN1(R)) -> P, then GN2(P) + X -> X, ReLU
                 const size_t n_ops = net->ops.size();
                 ConvOp& c1 = net->ops[n_ops - (proj ? 3 : 2)];
                 ConvOp& c2 = net->ops[n_ops - 1];
-                c1.gn_out = BR; c1.gn_relu = 1;
+                c1.gn_aff = 0;
+                c2.gn_aff = 2; c2.gn_out = BX;
                 if (proj) {
                     ConvOp& pj = net->ops[n_ops - 2];
-                    pj.gn_out = BP; pj.gn_relu = 0;
-                    c2.out_buf = BX; c2.gn_out = BX; c2.gn_res = BP; c2.gn_relu = 1;
+                    pj.gn_aff = 1;
+                    c2.out_buf = BX; c2.gn_res = BP; c2.gn_res_aff = 1;
                 } else {
-                    c2.out_buf = BP; c2.gn_out = BX; c2.gn_res = BX; c2.gn_relu = 1;
+                    c2.out_buf = BP; c2.gn_res = BX; c2.gn_res_aff = -1;
                 }
             }
             C = wdt;
@@ -665,6 +705,13 @@ size_t buf_bytes(const af_net* net, int64_t batch) {
 size_t amax_bytes(const af_net* net, int64_t batch) {
     return net->prec == AF_FP8 ? align_up((size_t)net->n_slots * batch * 4, 256) : 0;
 }
+// GroupNorm nets: the statistics buffer, then three slots of scales and shifts
+size_t gn_stats_bytes(const af_net* net, int64_t batch) {
+    return align_up((size_t)batch * net->gn_stats_elems * 4, 256);
+}
+size_t gn_aff_bytes(const af_net* net, int64_t batch) {
+    return align_up((size_t)batch * net->gn_aff_elems * 4, 256);
+}
 }  // namespace
 
 namespace {
@@ -691,7 +738,8 @@ bool launch_stem(af_precision p, const af_net_desc& d, const StemArgs& sa, int n
 
 extern "C" size_t af_score_workspace_bytes(const af_net* net, int64_t batch) {
     if (!net || batch < 1) return 0;
-    return 3 * buf_bytes(net, batch) + amax_bytes(net, batch);
+    return 3 * buf_bytes(net, batch) + amax_bytes(net, batch) + gn_stats_bytes(net, batch) +
+           3 * gn_aff_bytes(net, batch);
 }
 
 namespace {
@@ -734,11 +782,7 @@ void launch_gn(const af_net* net, const void* in, const void* res, void* out, si
     g.gamma = net->d_gn + gn_off;
     g.beta = g.gamma + C;
     g.L = L; g.C = C; g.G = net->gn_groups; g.relu = relu; g.pool = pool;
-    constexpr int NT = 1024, R = 6;   // threads and float4s per thread of the register-resident form
-    if (!pool && C <= 256 && (int64_t)L * C <= 4LL * NT * R)
-        hipLaunchKernelGGL((gn_reg_kernel<NT, R>), dim3((unsigned)nb), dim3(NT), 0, s, g);
-    else
-        hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
+    hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
 }
 }
 
@@ -821,6 +865,14 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
     const size_t bb = buf_bytes(net, batch);
     void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
     uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
+    float* gn_stats = nullptr;
+    float* gn_aff[3] = {nullptr, nullptr, nullptr};
+    if (net->gn_groups) {
+        char* g0 = (char*)ws + 3 * bb + amax_bytes(net, batch);
+        gn_stats = (float*)g0;
+        for (int k = 0; k < 3; ++k)
+            gn_aff[k] = (float*)(g0 + gn_stats_bytes(net, batch) + k * gn_aff_bytes(net, batch));
+    }
     const af_net_desc& d = net->desc;
     af_net* mnet = const_cast<af_net*>(net);  // timing records only; the weights stay read-only
     auto t_begin = [&](int layer, int64_t nw) -> bool {
@@ -909,14 +961,39 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
                 hipLaunchKernelGGL(channel_sum_kernel, dim3((unsigned)op.c_in), dim3(256), 0, s,
                                    (const float*)buf[op.in_buf], (int64_t)nb * op.l_in, op.c_in,
                                    net->d_tap + (size_t)(layer - 1) * net->tap_pitch);
+            if (net->gn_groups) {
+                a.gn_stats = gn_stats;
+                a.in_aff = op.in_buf == BR ? gn_aff[0] : nullptr;
+            }
             if (!t_begin(layer, nb)) { set_error("profiling event failed"); return AF_EHIP; }
             op.cfg.fn(a, s);
             AF_LAUNCHED();
             t_end();
-            if (net->gn_groups && !gn(buf[op.out_buf], op.gn_res >= 0 ? buf[op.gn_res] : nullptr, buf[op.gn_out],
-                                      op.gn_off, op.l_out, op.c_out, op.gn_relu, 0)) {
-                set_error("GroupNorm launch failed: %s", hipGetErrorString(hipGetLastError()));
-                return AF_EHIP;
+            if (net->gn_groups) {
+                // the statistics become this conv's scales and shifts; a
+                // block's second conv then ends the block
+                if (!t_begin(gn_layer, nb)) { set_error("profiling event failed"); return AF_EHIP; }
+                hipLaunchKernelGGL(gn_finalize_kernel, dim3((unsigned)nb), dim3(256), 0, s, (const float*)gn_stats,
+                                   (op.l_out + 15) / 16, op.l_out, op.c_out, net->gn_groups,
+                                   (const float*)net->d_gn + op.gn_off, (const float*)net->d_gn + op.gn_off + op.c_out,
+                                   gn_aff[op.gn_aff]);
+                AF_LAUNCHED();
+                if (op.gn_out >= 0) {
+                    GnApplyArgs g{};
+                    g.in = (const float*)buf[op.out_buf];
+                    g.res = (const float*)buf[op.gn_res];
+                    g.out = (float*)buf[op.gn_out];
+                    g.aff = gn_aff[op.gn_aff];
+                    g.res_aff = op.gn_res_aff >= 0 ? gn_aff[op.gn_res_aff] : nullptr;
+                    g.LC4 = op.l_out * op.c_out / 4;
+                    g.C = op.c_out;
+                    g.relu = 1;
+                    constexpr int U = 4;
+                    g.n_slice = (g.LC4 + 256 * U - 1) / (256 * U);
+                    hipLaunchKernelGGL(gn_apply_kernel<U>, dim3((unsigned)(g.n_slice * nb)), dim3(256), 0, s, g);
+                    AF_LAUNCHED();
+                }
+                t_end();
             }
         }
         if (!t_begin(layer + 1, nb)) { set_error("profiling event failed"); return AF_EHIP; }
@@ -1101,6 +1178,17 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
     const size_t bb = buf_bytes(net, batch);
     void* buf[3] = {ws, (char*)ws + bb, (char*)ws + 2 * bb};
     uint32_t* amax = net->prec == AF_FP8 ? (uint32_t*)((char*)ws + 3 * bb) : nullptr;
+    // GroupNorm nets: statistics, then the scales and shifts the second conv
+    // of a block reads (zero while timing)
+    float* gn_stats = nullptr;
+    const float* gn_aff0 = nullptr;
+    if (net->gn_groups) {
+        char* g0 = (char*)ws + 3 * bb + amax_bytes(net, batch);
+        gn_stats = (float*)g0;
+        gn_aff0 = (const float*)(g0 + gn_stats_bytes(net, batch));
+        const int64_t gw = (int64_t)((gn_stats_bytes(net, batch) + gn_aff_bytes(net, batch)) / 4);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((gw + 255) / 256)), dim3(256), 0, s, (uint32_t*)g0, gw, 0u);
+    }
     // defined contents: activations zero, FP8 maxima 1.0
     const int64_t words = (int64_t)(3 * bb / 4);
     hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((words + 255) / 256)), dim3(256), 0, s, (uint32_t*)ws, words, 0u);
@@ -1179,6 +1267,8 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
             a.C_in = op.c_in; a.C_out = op.c_out; a.L_in = op.l_in; a.L_out = op.l_out;
             a.relu = op.relu; a.n_win = (int)batch;
             a.wpt = trial.wpt; a.tt = trial.tt; a.tiles_per_win = trial.tiles_per_win;
+            a.gn_stats = gn_stats;
+            a.in_aff = net->gn_groups && op.in_buf == BR ? gn_aff0 : nullptr;
             trial.cfg.fn(a, s);   // warm-up
             (void)hipEventRecord(e0, s);
             for (int rep = 0; rep < 3; ++rep) trial.cfg.fn(a, s);

@@ -107,6 +107,26 @@ struct PFP8X {
     static constexpr bool kFP8 = true;
 };
 
+// GroupNorm forms of the FP32-activation traits: the conv also writes, per
+// window, channel and 16-row block of its output, the sum and the sum of
+// squares of the block's values (GroupNorm statistics, reduced later in a
+// fixed order whatever the tile shape), and with AFF it normalises its input
+// as it stages it: relu(x scale + shift) with the per-window, per-channel
+// scale and shift of the previous conv's GroupNorm (zero padding stays zero).
+template <typename B, bool AFF>
+struct PGn : B {
+    static constexpr bool kGnStats = true;
+    static constexpr bool kGnAff = AFF;
+};
+template <typename P, typename = void>
+struct GnTraits {
+    static constexpr bool stats = false, aff = false;
+};
+template <typename P>
+struct GnTraits<P, std::void_t<decltype(P::kGnStats)>> {
+    static constexpr bool stats = P::kGnStats, aff = P::kGnAff;
+};
+
 template <typename P>
 __device__ __forceinline__ float act_to_f32(typename P::Act v) {
     if constexpr (sizeof(typename P::Act) == 4) return v;
@@ -211,6 +231,11 @@ struct ConvArgs {
     int tiles_per_win;     // M tiles per window when wpt == 1
     int relu;
     int n_mtiles;          // M tiles (set by the launcher)
+    // GroupNorm forms: per window and 16-row output block, sums then sums of
+    // squares over the block's rows, [B][ceil(L_out/16)][2][C_out]; and the
+    // input's scale then shift, [B][2][C_in]
+    float* gn_stats;
+    const float* in_aff;
 };
 
 // LDS layout of the 16-byte operand reads of gfx950 (ds_read_b128 by 64
@@ -421,6 +446,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     int s_off[RA];
     bool f_ok[RA], s_ok[RA];
     float s_sc[RA];
+    int f_w[RA];   // window of the vector within the tile (GroupNorm input scaling)
 #pragma unroll
     for (int i = 0; i < RA; ++i) {
         const int v = tid + i * NTH;
@@ -433,17 +459,34 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         f_ok[i] = s_ok[i] && win < a.n_win && gr >= 0 && gr < a.L_in;
         f_off[i] = f_ok[i] ? (w * a.L_in + gr) * a.C_in + q * AE : 0;
         s_off[i] = rr * PA + q * AE;
+        f_w[i] = w;
         float sc = inv_a[0];
 #pragma unroll
         for (int u = 1; u < WMAX; ++u) sc = (w == u) ? inv_a[u] : sc;
         s_sc[i] = sc;
     }
+    // GroupNorm input scaling: a thread's vectors all start at channel
+    // q * AE of the chunk (NTH is a multiple of AV_ROW), so per chunk it needs
+    // one scale and one shift vector per window of the tile
+    constexpr bool GAFF = GnTraits<P>::aff;
+    static_assert(!GAFF || (sizeof(Act) == 4 && NTH % AV_ROW == 0), "GroupNorm input scaling reads FP32 rows");
+    const int q_t = tid % AV_ROW;
+    float4 gsc[GAFF ? WMAX : 1], gsh[GAFF ? WMAX : 1];
 #define AFM_FETCH(CC)                                                                              \
     {                                                                                              \
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
             uint4 x = make_uint4(0u, 0u, 0u, 0u);                                                  \
             if (f_ok[i]) x = *(const uint4*)(in_t + f_off[i] + (CC) * KC);                         \
             ra[i] = x;                                                                             \
+        }                                                                                          \
+        if constexpr (GAFF) {                                                                      \
+            _Pragma("unroll") for (int u = 0; u < WMAX; ++u) {                                    \
+                const int wu = win0 + (u < wpt ? u : 0);                                           \
+                const float* ap_ = a.in_aff + (size_t)(wu < a.n_win ? wu : a.n_win - 1) * 2 * a.C_in \
+                                   + (CC) * KC + q_t * AE;                                         \
+                gsc[u] = *(const float4*)ap_;                                                      \
+                gsh[u] = *(const float4*)(ap_ + a.C_in);                                           \
+            }                                                                                      \
         }                                                                                          \
     }
 #define AFM_WLOAD(RWV, CC, BUF)                                                                    \
@@ -476,6 +519,17 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
             if (s_ok[i]) {                                                                         \
                 Op* dst = slab_ + s_off[i];                                                        \
+                if constexpr (GAFF) {                                                              \
+                    float4 sc_ = gsc[0], sh_ = gsh[0];                                             \
+                    _Pragma("unroll") for (int u = 1; u < WMAX; ++u)                              \
+                        if (f_w[i] == u) { sc_ = gsc[u]; sh_ = gsh[u]; }                           \
+                    if (f_ok[i])                                                                   \
+                        ra[i] = make_uint4(                                                        \
+                            __float_as_uint(fmaxf(fmaf(__uint_as_float(ra[i].x), sc_.x, sh_.x), 0.f)), \
+                            __float_as_uint(fmaxf(fmaf(__uint_as_float(ra[i].y), sc_.y, sh_.y), 0.f)), \
+                            __float_as_uint(fmaxf(fmaf(__uint_as_float(ra[i].z), sc_.z, sh_.z), 0.f)), \
+                            __float_as_uint(fmaxf(fmaf(__uint_as_float(ra[i].w), sc_.w, sh_.w), 0.f))); \
+                }                                                                                  \
                 if constexpr (sizeof(Act) == 4 && sizeof(Op) == 2) {                               \
                     const uint4 f = ra[i];                                                         \
                     *(uint2*)dst = make_uint2(pack_bf16x2(__uint_as_float(f.x), __uint_as_float(f.y)),  \
@@ -735,6 +789,29 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #pragma unroll
             for (int u = 0; u < WMAX; ++u)
                 if (w == u) vmax[u] = fmaxf(vmax[u], m);
+        }
+    }
+    if constexpr (GnTraits<P>::stats) {
+        // GroupNorm statistics of this phase's 16-row blocks (tt and t0 are
+        // multiples of 16, so a block lies in one window and starts at a
+        // multiple of 16): per column, the values as stored (no residual or
+        // ReLU on these convs), summed over the block's rows in order
+        const int nblk = (a.L_out + 15) >> 4;
+        for (int item = tid; item < (MTP / 16) * NT; item += NTH) {
+            const int gi = item / NT, col = item % NT;
+            const int row0 = ph * MTP + gi * 16;
+            const int w = row0 / tt, t = t0 + row0 % tt;
+            if (win0 + w >= a.n_win || t >= a.L_out) continue;
+            const float bc = a.bias[n0 + col];
+            float sum = 0.f, sq = 0.f;
+            for (int r = 0; r < 16 && t + r < a.L_out; ++r) {
+                const float x = et[(gi * 16 + r) * EPITCH + col] + bc;
+                sum += x;
+                sq = fmaf(x, x, sq);
+            }
+            float* st = a.gn_stats + ((size_t)(win0 + w) * nblk + (t >> 4)) * 2 * a.C_out + n0 + col;
+            st[0] = sum;
+            st[a.C_out] = sq;
         }
     }
     }   // epilogue phases
