@@ -471,7 +471,7 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
     constexpr bool GAFF = GnTraits<P>::aff;
     static_assert(!GAFF || (sizeof(Act) == 4 && NTH % AV_ROW == 0), "GroupNorm input scaling reads FP32 rows");
     const int q_t = tid % AV_ROW;
-    float4 gsc[GAFF ? WMAX : 1], gsh[GAFF ? WMAX : 1];
+    float4 gsc[GAFF ? WMAX : 1] = {}, gsh[GAFF ? WMAX : 1] = {};
 #define AFM_FETCH(CC)                                                                              \
     {                                                                                              \
         _Pragma("unroll") for (int i = 0; i < RA; ++i) {                                          \
@@ -481,11 +481,13 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
         }                                                                                          \
         if constexpr (GAFF) {                                                                      \
             _Pragma("unroll") for (int u = 0; u < WMAX; ++u) {                                    \
-                const int wu = win0 + (u < wpt ? u : 0);                                           \
-                const float* ap_ = a.in_aff + (size_t)(wu < a.n_win ? wu : a.n_win - 1) * 2 * a.C_in \
-                                   + (CC) * KC + q_t * AE;                                         \
-                gsc[u] = *(const float4*)ap_;                                                      \
-                gsh[u] = *(const float4*)(ap_ + a.C_in);                                           \
+                if (u == 0 || u < wpt) {                                                           \
+                    const int wu = win0 + u;                                                       \
+                    const float* ap_ = a.in_aff + (size_t)(wu < a.n_win ? wu : a.n_win - 1) * 2 * a.C_in \
+                                       + (CC) * KC + q_t * AE;                                     \
+                    gsc[u] = *(const float4*)ap_;                                                  \
+                    gsh[u] = *(const float4*)(ap_ + a.C_in);                                       \
+                }                                                                                  \
             }                                                                                      \
         }                                                                                          \
     }
@@ -521,8 +523,10 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
                 Op* dst = slab_ + s_off[i];                                                        \
                 if constexpr (GAFF) {                                                              \
                     float4 sc_ = gsc[0], sh_ = gsh[0];                                             \
-                    _Pragma("unroll") for (int u = 1; u < WMAX; ++u)                              \
-                        if (f_w[i] == u) { sc_ = gsc[u]; sh_ = gsh[u]; }                           \
+                    if (wpt > 1) {   /* several windows per tile (uniform) */                      \
+                        _Pragma("unroll") for (int u = 1; u < WMAX; ++u)                          \
+                            if (f_w[i] == u) { sc_ = gsc[u]; sh_ = gsh[u]; }                       \
+                    }                                                                              \
                     if (f_ok[i])                                                                   \
                         ra[i] = make_uint4(                                                        \
                             __float_as_uint(fmaxf(fmaf(__uint_as_float(ra[i].x), sc_.x, sh_.x), 0.f)), \
@@ -671,6 +675,47 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #undef AFM_WLOAD
 #undef AFM_STASH
 
+    if constexpr (GnTraits<P>::stats) {
+        // GroupNorm statistics, straight from the accumulators: tile i of a
+        // wave is one 16-row block of the output (tt and t0 are multiples of
+        // 16, so the block lies in one window and starts at a multiple of
+        // 16), whose column r16 this lane holds at rows 4g .. 4g + 3.  These
+        // convs have no bias, residual or ReLU, so the accumulators are the
+        // values stored.  They are summed in the lane in row order, then
+        // across the lane groups (xor 16, then xor 32): the same order
+        // whatever the tile shape.
+        const int nblk = (a.L_out + 15) >> 4;
+#pragma unroll
+        for (int i = 0; i < TM; ++i) {
+            const int row0 = (wm * TM + i) * 16;
+            const int w = row0 / tt, tb = t0 + row0 % tt;
+            const bool ok = win0 + w < a.n_win && tb < a.L_out;
+            const int nval = a.L_out - tb;   // rows of the block inside the output (> 16: all)
+#pragma unroll
+            for (int jn = 0; jn < TN; ++jn) {
+                const int col = (wn * TN + jn) * 16 + r16;
+                float sum = 0.f, sq = 0.f;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    if (g * 4 + r < nval) {
+                        const float x = acc[i][jn][r];
+                        sum += x;
+                        sq = fmaf(x, x, sq);
+                    }
+                }
+                sum += __shfl_xor(sum, 16);
+                sq += __shfl_xor(sq, 16);
+                sum += __shfl_xor(sum, 32);
+                sq += __shfl_xor(sq, 32);
+                if (ok && g == 0) {
+                    float* st = a.gn_stats + ((size_t)(win0 + w) * nblk + (tb >> 4)) * 2 * a.C_out + n0 + col;
+                    st[0] = sum;
+                    st[a.C_out] = sq;
+                }
+            }
+        }
+    }
+
     // epilogue: the accumulators go through LDS so that bias, dequant,
     // residual, ReLU, rounding and the stores run on 16-byte row vectors
     float* et = (float*)smem_raw;
@@ -789,29 +834,6 @@ __global__ void __launch_bounds__(64 * WM * WN, (conv_waves_per_eu<P, WM, WN, TM
 #pragma unroll
             for (int u = 0; u < WMAX; ++u)
                 if (w == u) vmax[u] = fmaxf(vmax[u], m);
-        }
-    }
-    if constexpr (GnTraits<P>::stats) {
-        // GroupNorm statistics of this phase's 16-row blocks (tt and t0 are
-        // multiples of 16, so a block lies in one window and starts at a
-        // multiple of 16): per column, the values as stored (no residual or
-        // ReLU on these convs), summed over the block's rows in order
-        const int nblk = (a.L_out + 15) >> 4;
-        for (int item = tid; item < (MTP / 16) * NT; item += NTH) {
-            const int gi = item / NT, col = item % NT;
-            const int row0 = ph * MTP + gi * 16;
-            const int w = row0 / tt, t = t0 + row0 % tt;
-            if (win0 + w >= a.n_win || t >= a.L_out) continue;
-            const float bc = a.bias[n0 + col];
-            float sum = 0.f, sq = 0.f;
-            for (int r = 0; r < 16 && t + r < a.L_out; ++r) {
-                const float x = et[(gi * 16 + r) * EPITCH + col] + bc;
-                sum += x;
-                sq = fmaf(x, x, sq);
-            }
-            float* st = a.gn_stats + ((size_t)(win0 + w) * nblk + (t >> 4)) * 2 * a.C_out + n0 + col;
-            st[0] = sum;
-            st[a.C_out] = sq;
         }
     }
     }   // epilogue phases
