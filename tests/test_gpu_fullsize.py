@@ -2,7 +2,8 @@
 configuration, checked on sampled outputs that the FP64 oracle recomputes one
 by one (PSD of sampled hops, whitened samples of sampled windows, logits of
 those windows in FP32 and in every reduced-precision mode at the 8192-window
-batch, one integrated value)."""
+batch, one integrated value, and the GroupNorm network's logits in FP32 and
+with BF16 operands)."""
 import numpy as np
 import pytest
 import torch
@@ -109,3 +110,36 @@ def test_sampled_windows_reduced_precision(hour_run, lowp_logits, prec, k):
     err = abs(lowp_logits[prec][k] - logit_ref)
     print(f"{prec} window {k}: |dlogit| {err:.3e}")
     assert err < LOWP_TOL[prec]
+
+
+GN_TOL = {"f32": 1e-3, "bf16f": 3e-2}
+
+
+@pytest.fixture(scope="module")
+def gn_logits(hour_run):
+    """Logits of all 57,600 windows by the GroupNorm ResNet34 at 64-512
+    channels, FP32 and BF16 operands, autotuned and scored at the benchmark's
+    8192-window batch."""
+    P = need_gpu()
+    from synth import GN_ARCH
+    params = make_params(GN_ARCH, seed=0)
+    y = torch.from_numpy(hour_run["y"]).cuda()
+    out = {}
+    for prec in GN_TOL:
+        banner(f"full-size hour workload, GroupNorm net, {prec}")
+        net = P.Net(GN_ARCH, params, prec)
+        net.autotune(batch=2048)
+        out[prec] = net.score_windows(y, STRIDE, hour_run["n_windows"], batch=8192).cpu().numpy()
+    return params, out
+
+
+@pytest.mark.parametrize("prec", list(GN_TOL))
+@pytest.mark.parametrize("k", [0, 20000, 57599])
+def test_sampled_windows_groupnorm_net(hour_run, gn_logits, prec, k):
+    from synth import GN_ARCH
+    params, logits = gn_logits
+    y_ref, _ = oracle_window(hour_run["x"], hour_run["params"], k)
+    ref = oracle.net_forward_gn(params, GN_ARCH, y_ref[None])[0]
+    err = abs(logits[prec][k] - ref)
+    print(f"GroupNorm net {prec} window {k}: |dlogit| {err:.3e}")
+    assert err < GN_TOL[prec]

@@ -108,3 +108,51 @@ def test_graph_replays_after_a_tile_switch():
         np.testing.assert_array_equal(plan.logits[:plan.n_windows].cpu().numpy(), direct)
     np.testing.assert_array_equal(P.score_timeslides(net, y, seg_off, seg_len, shifts, stride=1024).cpu().numpy(),
                                   direct)
+
+
+def test_full_day_sampled_windows():
+    # the benchmark's timeslide workload at full size (24 h in 40 lognormal
+    # segments, 100 slides of k x 1 s, 1 Hz windows, the autotuned whole-network
+    # kernel in a hipGraph) on a seeded stand-in for the whitened series;
+    # sampled windows, wrap-crossing ones included, against the oracle
+    P = need_gpu()
+    import torch
+    from paper_2403_18661_amd.timeslides import TimeslidePlan
+    from synth import lognormal_segments
+    banner("timeslides, full day, sampled windows")
+    fs, stride, W = 2048, 2048, TINY_ARCH.window
+    seg_len = [int(d) * fs - 133120 for d in lognormal_segments(seed=0)]
+    seg_len = [L for L in seg_len if L >= W]
+    seg_off = list(np.cumsum([0] + seg_len[:-1]))
+    y = np.random.default_rng(15).standard_normal((2, sum(seg_len)), dtype=np.float32)
+    shifts = [k * fs for k in range(1, 101)]
+    params = make_params(TINY_ARCH, seed=0)
+    net = P.Net(TINY_ARCH, params, "bf16")
+    net.autotune(batch=8192)
+    plan = TimeslidePlan(net, dev(y), seg_off, seg_len, shifts, stride=stride, graph=True)
+    plan.run()
+    plan.stream.synchronize()
+    got = plan.logits[:plan.n_windows].cpu().numpy()
+    assert plan.n_windows == P.timeslide_n_windows(seg_len, len(shifts), W, stride) > 8_000_000
+    nw = [(L - W) // stride + 1 for L in seg_len]
+    base = np.cumsum([0] + [n * len(shifts) for n in nw[:-1]])
+    rng = np.random.default_rng(16)
+    picks = [(0, 0, 0), (len(seg_len) - 1, 99, nw[-1] - 1)]
+    for s in rng.choice(len(seg_len), 6, replace=False):
+        k = int(rng.integers(100))
+        # the last window of a slide: its L1 part wraps past the segment's end
+        picks += [(int(s), k, nw[s] - 1), (int(s), k, int(rng.integers(nw[s])))]
+    wins, idx = [], []
+    for s, k, i in picks:
+        o, L = seg_off[s], seg_len[s]
+        t = i * stride + np.arange(W)
+        wins.append(np.stack([y[0, o + t], y[1, o + (t + shifts[k]) % L]]).astype(np.float64))
+        idx.append(base[s] + k * nw[s] + i)
+    wins = np.stack(wins)
+    ref = oracle.net_forward(params, TINY_ARCH, wins)
+    emu = oracle.net_forward_quant(params, TINY_ARCH, wins, "bf16")
+    err, err_emu = np.abs(got[idx] - ref).max(), np.abs(got[idx] - emu).max()
+    print(f"{len(idx)} sampled windows of {plan.n_windows}: |d| vs FP64 {err:.2e}, vs BF16 emulation {err_emu:.2e}")
+    assert err < 3e-2 and err_emu < 2e-5
+    del plan
+    torch.cuda.empty_cache()
