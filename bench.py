@@ -292,12 +292,11 @@ def gn_bytes(arch, windows):
     of squares per channel and 16-row block) and writes a scale and a shift
     per channel; per block, the apply kernel reads the second conv's FP32
     output and the skip once and writes the block output once (the first
-    conv's norm is applied inside the second conv as it loads its input).  A
-    32-channel stem's norm runs inside the stem kernel and is timed with it;
-    a wider stem's reads the raw stem output and writes the pooled one."""
+    conv's norm is applied inside the second conv as it loads its input).  The
+    stem's norm runs inside the stem kernel and is timed with it."""
     l_conv = (arch.window + 2 * (arch.kernel // 2) - arch.kernel) // arch.stem_stride + 1
     L = (l_conv - 1) // 2 + 1 if arch.stem_pool else l_conv
-    b = 0 if arch.stem_ch == 32 else (l_conv + L) * arch.stem_ch
+    b = 0
     for _, _, c_out, stride, proj in arch.block_list():
         lo = (L - 1) // stride + 1
         n_conv = 3 if proj else 2

@@ -6,25 +6,32 @@
 // into per-channel scales and shifts; the block's second conv applies the
 // first one's as it stages its input, and gn_apply_kernel ends the block
 // (second norm, the projection's norm on the skip, residual add, ReLU).  The
-// stem's norm runs in the stem kernel or in gn_kernel.
+// stem's norm runs inside the stem kernel.
 #pragma once
 
 #include "net_kernels.h"
 
 namespace afm {
 
-// Raw stem conv: out[b][t][c] = sum over input channels ci and taps j of
-// w[c][ci][j] x_ci[t s0 + j - (KW-1)/2] (zero outside the window), FP32
-// vector arithmetic, no bias, no ReLU, no pool; out is [B][L_conv][C].  C
-// divides 256, so each thread keeps one channel (its weights in registers)
-// and steps through the rows 256 / C at a time.
+// The GroupNorm net's stem for any width C dividing 256: conv, GroupNorm,
+// ReLU and (with a.pool) max-pool k3 s2 p1, one window per workgroup of 256
+// threads, writing only the stem's output.  The conv (NCH x KW taps per
+// output) is cheap, so it is computed twice instead of being stored: pass 1
+// accumulates per-channel sums and sums of squares in FP64 (thread t takes
+// channel t % C and rows t / C, t / C + 256 / C, ...), reduced across the
+// threads of a channel, then per group in channel order; pass 2 recomputes
+// each conv value where the output needs it, normalises it and applies ReLU
+// (and the pool: every candidate is >= 0, so 0 starts the max).  Samples are
+// staged in LDS; weights in registers.
 template <int NCH, int KW>
-__global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a) {
+__global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a, const float* gamma, const float* beta, int G) {
     extern __shared__ float xs[];  // [n_ch][window]
-    const int b = blockIdx.x;
+    __shared__ double part[2][256];
+    __shared__ float sc[256], sh[256];
+    const int b = blockIdx.x, tid = threadIdx.x;
     const WinAddr wa = window_addr(a, a.first_window + b);
     stage_window(a, wa, xs);
-    const int C = a.C, W = a.window, c = threadIdx.x % C, rstep = 256 / C;
+    const int C = a.C, W = a.window, c = tid % C, rstep = 256 / C;
     float w[NCH][KW];
 #pragma unroll
     for (int ci = 0; ci < NCH; ++ci)
@@ -32,19 +39,65 @@ __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a) {
         for (int j = 0; j < KW; ++j) w[ci][j] = a.w[(c * NCH + ci) * KW + j];
     __syncthreads();
     constexpr int pad = (KW - 1) / 2;
-    float* out = (float*)a.out + (size_t)b * a.L_conv * C;
-    for (int t = threadIdx.x / C; t < a.L_conv; t += rstep) {
+    auto conv = [&](int t) {
         const int q0 = t * a.s0 - pad;
-        float s = 0.f;
+        float acc = 0.f;
 #pragma unroll
         for (int ci = 0; ci < NCH; ++ci)
 #pragma unroll
             for (int j = 0; j < KW; ++j) {
                 const int q = q0 + j;
                 const float x = (q >= 0 && q < W) ? xs[ci * W + q] : 0.f;
-                s = fmaf(w[ci][j], x, s);
+                acc = fmaf(w[ci][j], x, acc);
             }
-        out[(size_t)t * C + c] = s;
+        return acc;
+    };
+    double s = 0.0, q = 0.0;
+    for (int t = tid / C; t < a.L_conv; t += rstep) {
+        const double v = conv(t);
+        s += v;
+        q += v * v;
+    }
+    part[0][tid] = s;
+    part[1][tid] = q;
+    __syncthreads();
+    if (tid < C) {
+        // thread tid's channel sums: slots tid, tid + C, ... in order, then the group
+        double cs = 0.0, cq = 0.0;
+        for (int k = tid; k < 256; k += C) {
+            cs += part[0][k];
+            cq += part[1][k];
+        }
+        part[0][tid] = cs;   // slot tid was read above by this thread only
+        part[1][tid] = cq;
+    }
+    __syncthreads();
+    if (tid < C) {
+        const int cpg = C / G, g = tid / cpg;
+        double gs = 0.0, gq = 0.0;
+        for (int cc = g * cpg; cc < (g + 1) * cpg; ++cc) {
+            gs += part[0][cc];
+            gq += part[1][cc];
+        }
+        const double n = (double)cpg * a.L_conv;
+        const double mean = gs / n;
+        const double var = fmax(gq / n - mean * mean, 0.0);
+        const double scale = (double)gamma[tid] / sqrt(var + 1e-5);
+        sc[tid] = (float)scale;
+        sh[tid] = (float)((double)beta[tid] - mean * scale);
+    }
+    __syncthreads();
+    const float S = sc[c], H = sh[c];
+    float* out = (float*)a.out + (size_t)b * a.L_out * C;
+    for (int p = tid / C; p < a.L_out; p += rstep) {
+        float m = 0.f;
+        if (a.pool) {
+            for (int r = 2 * p - 1; r <= 2 * p + 1; ++r)
+                if (r >= 0 && r < a.L_conv) m = fmaxf(m, fmaf(conv(r), S, H));
+        } else {
+            m = fmaxf(fmaf(conv(p), S, H), 0.f);
+        }
+        out[(size_t)p * C + c] = m;
     }
 }
 
@@ -147,120 +200,6 @@ __global__ void __launch_bounds__(1024) gn_stem_fused_kernel(StemArgs a, const f
             const float left = j == 0 ? prev : v[2 * j - 1];
             out[(size_t)(rb * (R / 2) + j) * 32 + c] = fmaxf(fmaxf(left, v[2 * j]), v[2 * j + 1]);
         }
-}
-
-struct GnArgs {
-    const float* in;      // [B][L][C]
-    const float* res;     // [B][L][C] added after the affine map, or null
-    float* out;           // [B][L_out][C]; may alias in or res when pool == 0
-    const float* gamma;   // [C]
-    const float* beta;    // [C]
-    int L, C, G;          // C a power of two in [16, 1024], G divides C
-    int relu;             // ReLU after the (residual) add
-    int pool;             // max-pool k3 s2 p1 after the ReLU (relu must be set)
-};
-
-// GroupNorm of one window per workgroup (256 threads).  Pass 1: per-channel
-// sums and sums of squares in FP64 (1024 is a multiple of C, so a thread's
-// four channels stay fixed as it strides through the window's float4s),
-// reduced per group in a fixed order: mean and biased variance, for channels
-// tid, tid + 256, ... .  Pass 2:
-// v * scale_c + shift_c with scale_c = gamma_c / sqrt(var_g + eps),
-// shift_c = beta_c - mean_g scale_c, then residual add, ReLU, pool.  Each
-// element of `out` is written by the thread that read it in pass 2, and pass 1
-// ends at a barrier, so out may alias in or res.
-__global__ void __launch_bounds__(256) gn_kernel(GnArgs a) {
-    constexpr int U = 8;   // float4 loads in flight per thread
-    __shared__ double part[2][1024];
-    __shared__ float sc[1024], sh[1024];
-    const int tid = threadIdx.x, C = a.C, L = a.L;
-    const size_t b = blockIdx.x;
-    const float4* in = (const float4*)(a.in + b * L * C);
-    const int n4 = L * C / 4;
-    double s[4] = {0.0, 0.0, 0.0, 0.0}, q[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int i0 = tid; i0 < n4; i0 += 256 * U) {
-        float4 v[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) v[u] = in[min(i0 + 256 * u, n4 - 1)];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            if (i0 + 256 * u >= n4) break;
-            const float e[4] = {v[u].x, v[u].y, v[u].z, v[u].w};
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                s[k] += (double)e[k];
-                q[k] += (double)e[k] * (double)e[k];
-            }
-        }
-    }
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        part[0][4 * tid + k] = s[k];
-        part[1][4 * tid + k] = q[k];
-    }
-    __syncthreads();
-    // slot p of part holds channel p % C; channel c of group g = c / (C / G)
-    for (int ch = tid; ch < C; ch += 256) {
-        const int cpg = C / a.G, g = ch / cpg;
-        double gs = 0.0, gq = 0.0;
-        for (int c = g * cpg; c < (g + 1) * cpg; ++c)
-            for (int p = c; p < 1024; p += C) {
-                gs += part[0][p];
-                gq += part[1][p];
-            }
-        const double n = (double)cpg * L;
-        const double mean = gs / n;
-        const double var = fmax(gq / n - mean * mean, 0.0);
-        const double scale = (double)a.gamma[ch] / sqrt(var + 1e-5);
-        sc[ch] = (float)scale;
-        sh[ch] = (float)((double)a.beta[ch] - mean * scale);
-    }
-    __syncthreads();
-    const int c0 = (4 * tid) % C;
-    const float4 S = make_float4(sc[c0], sc[c0 + 1], sc[c0 + 2], sc[c0 + 3]);
-    const float4 H = make_float4(sh[c0], sh[c0 + 1], sh[c0 + 2], sh[c0 + 3]);
-    auto norm = [&](float4 v) {
-        return make_float4(fmaf(v.x, S.x, H.x), fmaf(v.y, S.y, H.y), fmaf(v.z, S.z, H.z), fmaf(v.w, S.w, H.w));
-    };
-    auto relu4 = [](float4 v) {
-        return make_float4(fmaxf(v.x, 0.f), fmaxf(v.y, 0.f), fmaxf(v.z, 0.f), fmaxf(v.w, 0.f));
-    };
-    if (!a.pool) {
-        const float4* res = a.res ? (const float4*)(a.res + b * L * C) : nullptr;
-        float4* out = (float4*)(a.out + b * L * C);
-        for (int i0 = tid; i0 < n4; i0 += 256 * U) {
-            float4 v[U], r[U];
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const int i = min(i0 + 256 * u, n4 - 1);
-                v[u] = in[i];
-                r[u] = res ? res[i] : make_float4(0.f, 0.f, 0.f, 0.f);
-            }
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                if (i0 + 256 * u >= n4) break;
-                float4 y = norm(v[u]);
-                if (res) y = make_float4(y.x + r[u].x, y.y + r[u].y, y.z + r[u].z, y.w + r[u].w);
-                out[i0 + 256 * u] = a.relu ? relu4(y) : y;
-            }
-        }
-    } else {
-        // pooled row p takes rows 2p-1, 2p, 2p+1 of the normalised, ReLU'd
-        // input; every candidate is >= 0, so 0 starts the max
-        const int L_out = (L - 1) / 2 + 1, C4 = C / 4;
-        const int n4o = L_out * C4;
-        float4* out = (float4*)(a.out + b * L_out * C);
-        for (int i = tid; i < n4o; i += 256) {
-            const int p = i / C4, cq = i - p * C4;
-            float4 m = make_float4(0.f, 0.f, 0.f, 0.f);
-            for (int r = 2 * p - 1; r <= 2 * p + 1; ++r) {
-                if (r < 0 || r >= L) continue;
-                const float4 y = relu4(norm(in[r * C4 + cq]));
-                m = make_float4(fmaxf(m.x, y.x), fmaxf(m.y, y.y), fmaxf(m.z, y.z), fmaxf(m.w, y.w));
-            }
-            out[i] = m;
-        }
-    }
 }
 
 // GroupNorm scale and shift of one window per workgroup (256 threads) from

@@ -478,7 +478,7 @@ af_status create_net(const af_net_desc* d, int groups, const double* params, int
     net->stem_lout = d->stem_pool ? (net->stem_lconv + 2 - 3) / 2 + 1 : net->stem_lconv;
     net->macs = (int64_t)net->stem_lconv * d->stem_ch * d->in_ch * K;
     net->layer_macs.push_back(net->macs);
-    net->act_elems = (int64_t)(groups ? net->stem_lconv : net->stem_lout) * d->stem_ch;   // GN: raw stem output
+    net->act_elems = (int64_t)net->stem_lout * d->stem_ch;
 
     int L = net->stem_lout, C = d->stem_ch, slot_x = 0, n_slots = 1;
     auto add_conv = [&](int c_in, int c_out, int kw, int s, int l_in, int relu, int in_buf, int out_buf,
@@ -770,20 +770,6 @@ bool launch_fused(int cand, int n_cu, const FusedTinyArgs& fa, hipStream_t s) {
         default: return go(fused_tiny_bf16_kernel<64, 32, true>);
     }
 }
-
-// GroupNorm of nb windows of [L][C] FP32 activations (one workgroup each);
-// gamma and beta at gn_off of the net's table.
-void launch_gn(const af_net* net, const void* in, const void* res, void* out, size_t gn_off, int L, int C, int relu,
-               int pool, int nb, hipStream_t s) {
-    GnArgs g{};
-    g.in = (const float*)in;
-    g.res = (const float*)res;
-    g.out = (float*)out;
-    g.gamma = net->d_gn + gn_off;
-    g.beta = g.gamma + C;
-    g.L = L; g.C = C; g.G = net->gn_groups; g.relu = relu; g.pool = pool;
-    hipLaunchKernelGGL(gn_kernel, dim3((unsigned)nb), dim3(256), 0, s, g);
-}
 }
 
 extern "C" af_status af_score_windows(const af_net* net, const float* y, int64_t n_ch, int64_t ld_y, int64_t n,
@@ -904,11 +890,6 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
         sa.L_conv = net->stem_lconv; sa.L_out = net->stem_lout;
         const size_t stem_lds = (size_t)n_ch * window * sizeof(float);
         const int gn_layer = (int)net->layer_macs.size() - 1;
-        auto gn = [&](const void* in, const void* res, void* out, size_t off, int L, int C, int relu, int pool) {
-            if (!t_begin(gn_layer, nb)) return false;
-            launch_gn(net, in, res, out, off, L, C, relu, pool, nb, s);
-            return hipPeekAtLastError() == hipSuccess && t_end();
-        };
         if (!t_begin(0, nb)) { set_error("profiling event failed"); return AF_EHIP; }
         constexpr int STEM_MAXR = 48;
         if (net->gn_groups && d.stem_ch == 32 && d.stem_pool && net->stem_lconv % 64 == 0 &&
@@ -920,15 +901,12 @@ af_status score_batches(const af_net* net, const float* y, int64_t ld_y, int64_t
             AF_LAUNCHED();
             t_end();
         } else if (net->gn_groups) {
-            // raw stem conv into R, then GroupNorm, ReLU (and pool) into X
-            sa.out = buf[BR];
-            hipLaunchKernelGGL((gn_stem_kernel<2, 3>), dim3(nb), dim3(256), stem_lds, s, sa);
+            // conv, GroupNorm, ReLU (and pool) in two passes over the staged window into X
+            sa.out = buf[BX];
+            hipLaunchKernelGGL((gn_stem_kernel<2, 3>), dim3(nb), dim3(256), stem_lds, s, sa,
+                               (const float*)net->d_gn, (const float*)net->d_gn + d.stem_ch, net->gn_groups);
             AF_LAUNCHED();
             t_end();
-            if (!gn(buf[BR], nullptr, buf[BX], 0, net->stem_lconv, d.stem_ch, 1, d.stem_pool)) {
-                set_error("GroupNorm launch failed: %s", hipGetErrorString(hipGetLastError()));
-                return AF_EHIP;
-            }
         } else if (!launch_stem(net->prec, d, sa, nb, stem_lds, s)) {
             if (net->prec == AF_F32 || net->prec == AF_BF16_F32ACT)
                 hipLaunchKernelGGL(stem_kernel<PF32>, dim3(nb), dim3(256), stem_lds, s, sa);
