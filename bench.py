@@ -153,6 +153,8 @@ def timeslide_leg(args, P, log):
         f"{time.perf_counter() - t0:.1f} s")
     shifts = [k * fs for k in range(1, 101)]
     changed = net.autotune(batch=8192)
+    if args.timeslide_cand is not None:   # pin the whole-network kernel's candidate (profiled runs)
+        net.set_fused_tile(args.timeslide_cand)
     log(f"timeslide: autotune changed {changed}; rows per step {net.fused_tile()[0]}")
     plan = TimeslidePlan(net, y, seg_off, seg_len, shifts, stride=fs, graph=True)
     for _ in range(args.warmup):
@@ -460,6 +462,8 @@ def main():
                     help="run only the 24 h whitening leg (e.g. to profile its kernel) and print its JSON")
     ap.add_argument("--gn-only", action="store_true",
                     help="run only the GroupNorm-net leg on the 1 h workload and print its JSON")
+    ap.add_argument("--timeslide-cand", type=int, default=None,
+                    help="use this candidate of the whole-network kernel after autotuning (e.g. to profile one shape)")
     ap.add_argument("--timeslide-only", action="store_true",
                     help="run only the timeslide leg (e.g. to profile its kernel) and print its JSON")
     ap.add_argument("--streams", default="1,16,64")
