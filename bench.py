@@ -176,6 +176,12 @@ def timeslide_leg(args, P, log):
            "rows_per_step": net.fused_tile()[0],
            "achieved_tflops": flop / (ms * 1e-3) * 1e-12, "peak_tflops": PEAK_TFLOPS["bf16"],
            "frac": flop / (ms * 1e-3) * 1e-12 / PEAK_TFLOPS["bf16"], "kernel_ms": ms}
+    # HBM bytes per launch from the committed counter passes (null once the
+    # kernel sources differ from the profiled ones)
+    from paper_2403_18661_amd.profsum import read_traffic
+    pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "timeslide_kernel.txt"))
+    res["traffic_bytes_per_launch"] = pmc.get("timeslide", {}).get("traffic")
+    res["input_bytes_per_launch"] = 4 * 2 * TINY_ARCH.window * plan.n_windows
     log(f"timeslide: {res['value']:.0f} windows/s, {res['achieved_tflops']:.1f} TFLOP/s")
     res["events"] = events_leg(P, plan, seg_len, len(shifts), net.window, fs, log)
     del plan, y
@@ -315,6 +321,7 @@ def gn_leg(args, P, log, xd):
     import scipy.stats
     import torch
     from paper_2403_18661_amd.pipeline import OfflinePath, PathConfig
+    from paper_2403_18661_amd.profsum import read_traffic
     from synth import GN_ARCH, make_params
     from synth.workloads import PSD_LEN
     params = make_params(GN_ARCH, seed=0)
@@ -338,13 +345,17 @@ def gn_leg(args, P, log, xd):
         conv_tf = prof["flops"][1:nc + 1].sum() / args.steps / conv_ms * 1e-9
         gn_ms = prof["ms"][nc + 2] / args.steps
         gn_gbs = gn_bytes(GN_ARCH, path.n_windows) / (gn_ms * 1e-3) * 1e-9
+        pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                        "hour_workload_kernels.txt"))
         integ[prec] = path.integrated.cpu().numpy().astype(np.float64)
         out[prec] = {"value": path.n_windows * args.steps / dt, "ms_per_step": 1e3 * dt / args.steps,
                      "conv_ms_per_step": conv_ms, "conv_tflops": conv_tf, "conv_mfma_frac": conv_tf / PEAK_TFLOPS[prec],
                      "stem_ms_per_step": prof["ms"][0] / args.steps,
+                     "conv_traffic_bytes_per_launch": pmc.get(f"gn_{prec}_conv", {}).get("traffic"),
                      "groupnorm": {"ms_per_step": gn_ms, "launches_per_step": int(prof["launches"][nc + 2] // args.steps),
                                    "achieved": gn_gbs, "unit": "GB/s", "peak": PEAK_HBM_GBS,
-                                   "frac": gn_gbs / PEAK_HBM_GBS}}
+                                   "frac": gn_gbs / PEAK_HBM_GBS,
+                                   "apply_traffic_bytes_per_launch": pmc.get("gn_apply", {}).get("traffic")}}
         log(f"gn {prec}: {out[prec]['value']:.0f} windows/s, {out[prec]['ms_per_step']:.1f} ms/step, conv "
             f"{conv_tf:.1f} TFLOP/s ({conv_ms:.1f} ms), GroupNorm {gn_ms:.1f} ms ({gn_gbs:.0f} GB/s)")
         del path, net
@@ -567,6 +578,8 @@ def main():
             "layers": {"ms": prof["ms"].tolist(), "flops": prof["flops"].tolist(),
                        "launches": prof["launches"].tolist(), "tiles": net.tiles()},
         }
+        pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
+                                        "hour_workload_kernels.txt"))
         integ[prec] = path.integrated.cpu().numpy().astype(np.float64)
         log(f"{prec}: {res[prec]['value']:.0f} windows/s, {ms_step:.1f} ms/step, conv "
             f"{res[prec]['conv']['tflops']:.1f} TFLOP/s, stages {res[prec]['stages_ms']}")

@@ -252,8 +252,9 @@ af_status af_net_set_fused_tile(af_net* net, int32_t chosen);
 
 /* Number of timed layers: stem, each conv in execution order, GAP+FC head;
  * GroupNorm nets (af_net_create_gn) have one more, after the head, that
- * collects the separate GroupNorm launches (every block's; the stem's only
- * where it does not run inside the stem kernel, which is timed as layer 0). */
+ * collects the blocks' separate GroupNorm launches (scale and shift of every
+ * conv's norm, each block's end); the stem's norm runs inside the stem kernel
+ * (layer 0). */
 int64_t af_net_n_layers(const af_net* net);
 /* Kernel timing (a tracing aid, Sec. VIII reports per-stage latencies).
  * Between begin and end, every af_score_windows call on this net records a HIP
@@ -270,7 +271,9 @@ af_status af_net_profile_end(af_net* net, int64_t n_layers, double* ms, int64_t*
  * (rows x output channels per workgroup, LDS buffering); this times each one
  * on `batch` windows (contents of ws are overwritten; ws must hold
  * af_score_workspace_bytes(net, batch)) and keeps the fastest, rebuilding that
- * layer's weight image.  Synchronous; results are unchanged up to the
+ * layer's weight image.  The whole-network kernel's candidates are timed in
+ * its steady state instead: on 256 windows per CU (fewer if ws holds fewer)
+ * of ws read as a two-channel series.  Synchronous; results are unchanged up to the
  * tile-independent per-window arithmetic (the same logits bit for bit).
  * *n_changed (may be NULL) receives the number of layers switched. */
 af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_t ws_bytes, af_stream stream,

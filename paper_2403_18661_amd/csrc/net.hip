@@ -1181,17 +1181,25 @@ extern "C" af_status af_net_autotune(af_net* net, int64_t batch, void* ws, size_
     int64_t changed = 0;
     af_status result = AF_OK;
     if (net->fused_ok) {
-        // rows per step of the whole-network kernel: `batch` windows of the
-        // zeroed workspace read as a two-channel series (windows 2048 apart)
-        const int64_t n = (batch - 1) * 2048 + net->desc.window;
+        // rows per step of the whole-network kernel, timed in its steady
+        // state: 256 windows per CU (tens per persistent workgroup, so the
+        // last round's tail does not decide the ranking), read from the zeroed
+        // workspace as a two-channel series (windows 64 samples apart; the
+        // kernel's work per window does not depend on the data); fewer if the
+        // workspace holds fewer
+        const int64_t stride_t = 64, window = net->desc.window;
+        const int64_t cap = (int64_t)(3 * bb / sizeof(float));
+        int64_t nw_t = 256LL * net->n_cu;
+        while (nw_t > 1 && 2 * ((nw_t - 1) * stride_t + window) + nw_t + 1 > cap) nw_t /= 2;
+        const int64_t n = (nw_t - 1) * stride_t + window;
         FusedTinyArgs fa{};
         StemArgs& sa = fa.st;
-        sa.y = (const float*)ws; sa.ld_y = n; sa.n = n; sa.stride = 2048;
+        sa.y = (const float*)ws; sa.ld_y = n; sa.n = n; sa.stride = stride_t;
         sa.n_ch = 2; sa.window = net->desc.window;
         fa.wstem = net->d_sfused; fa.wconv = net->d_wfused; fa.bias = net->d_bfused; fa.fc = net->d_fc;
-        fa.logits = (float*)ws + 2 * n; fa.n_windows = batch;
-        fa.next = (unsigned int*)((float*)ws + 2 * n + batch);
-        AF_CHECK_ARG((size_t)(2 * n + batch + 1) * sizeof(float) <= 3 * bb, "workspace too small for batch %lld",
+        fa.logits = (float*)ws + 2 * n; fa.n_windows = nw_t;
+        fa.next = (unsigned int*)((float*)ws + 2 * n + nw_t);
+        AF_CHECK_ARG((size_t)(2 * n + nw_t + 1) * sizeof(float) <= 3 * bb, "workspace too small for batch %lld",
                      (long long)batch);
         int best = net->fused_cand;
         float best_ms = 1e30f;
