@@ -200,13 +200,20 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
             wave_lds_sync();
 
             // ---- conv layer l: buffer l -> buffer l + 1 (or the average)
-            auto conv = [&](const int l, const uint16_t* in, const uint16_t* res, uint16_t* out) {
+            // layer l (a compile-time constant): the second conv of a block
+            // (l odd) reads the block input as its eighth tap; the last one
+            // feeds the global average instead of a buffer
+            auto conv = [&](auto lc, const uint16_t* in, const uint16_t* res, uint16_t* out) {
+                constexpr int l = decltype(lc)::value;
+                constexpr bool RES = (l & 1) != 0, GAP = l == 3;
                 const uint16_t* bsrc[4];
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
                     const int j = 2 * s + (g >> 1), hf = g & 1;
-                    bsrc[s] = j < 7 ? in + act_off<PITCH, SWZ>(r16 + j, hf)
-                                    : (res ? res + act_off<PITCH, SWZ>(r16, hf) : in + act_off<PITCH, SWZ>(r16 + 6, hf));
+                    if (RES)
+                        bsrc[s] = j < 7 ? in + act_off<PITCH, SWZ>(r16 + j, hf) : res + act_off<PITCH, SWZ>(r16, hf);
+                    else
+                        bsrc[s] = in + act_off<PITCH, SWZ>(r16 + (j < 7 ? j : 6), hf);
                 }
                 f4v acc[NT];
 #pragma unroll
@@ -229,7 +236,7 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
 #pragma unroll
                 for (int m = 0; m < NT; ++m) {
                     const uint2 packed = finish_tile<EDGE>(acc[m], tl + 16 * m + r16, L);
-                    if (out) {
+                    if constexpr (!GAP) {
                         *(uint2*)(out + so + 16 * m * PITCH) = packed;
                     } else {
                         gs[0] += __uint_as_float(packed.x << 16);
@@ -239,13 +246,13 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
                     }
                 }
             };
-            conv(0, buf(0), nullptr, buf(1));   // block 0 conv1
+            conv(std::integral_constant<int, 0>{}, buf(0), nullptr, buf(1));   // block 0 conv1
             wave_lds_sync();
-            conv(1, buf(1), buf(0), buf(2));    // block 0 conv2 + block input
+            conv(std::integral_constant<int, 1>{}, buf(1), buf(0), buf(2));    // block 0 conv2 + block input
             wave_lds_sync();
-            conv(2, buf(2), nullptr, buf(3));   // block 1 conv1
+            conv(std::integral_constant<int, 2>{}, buf(2), nullptr, buf(3));   // block 1 conv1
             wave_lds_sync();
-            conv(3, buf(3), buf(2), nullptr);   // block 1 conv2 + block input -> average
+            conv(std::integral_constant<int, 3>{}, buf(3), buf(2), nullptr);   // block 1 conv2 + block input -> average
             wave_lds_sync();
 
             // carry the last TAIL rows of every buffer, and of the input, to the front
