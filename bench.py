@@ -55,7 +55,8 @@ def host_description():
                     break
     except OSError:
         pass
-    return {"nproc": os.cpu_count(), "cpu_model": model}
+    nproc = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else os.cpu_count()
+    return {"nproc": nproc, "cpu_count": os.cpu_count(), "cpu_model": model}
 
 
 def cpu_baseline(x, params, arch, n_windows=1536, n_windows_1core=128):

@@ -53,6 +53,23 @@ def test_gn_net_matches_oracle(arch, prec, nw):
         assert err < 1e-4 * max(1.0, np.abs(ref).max())
 
 
+@pytest.mark.parametrize("prec", ["f32", "bf16f"])
+def test_gn_edge_cases(prec):
+    # no windows, exactly one window (the series is one window long), and a
+    # window past the end rejected, at the standard widths
+    P = need_gpu()
+    banner(f"gn edge cases {prec}")
+    params = make_params(GN_ARCH, seed=64)
+    net = P.Net(GN_ARCH, params, prec)
+    y = series(GN_ARCH.window, seed=65)
+    assert net.score_windows(dev(y), 128, 0).numel() == 0
+    one = net.score_windows(dev(y), 128, 1).cpu().numpy()
+    ref = oracle_logits(params, GN_ARCH, y, 128, 1)
+    assert np.abs(one - ref).max() < TOL[prec]
+    with pytest.raises(P.AframeError, match="EINVAL"):
+        net.score_windows(dev(y), 128, 2)
+
+
 def test_gn_statistics_are_per_window():
     # a window's logit does not depend on the batch it is scored in
     P = need_gpu()
