@@ -579,8 +579,6 @@ def main():
             "layers": {"ms": prof["ms"].tolist(), "flops": prof["flops"].tolist(),
                        "launches": prof["launches"].tolist(), "tiles": net.tiles()},
         }
-        pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles",
-                                        "hour_workload_kernels.txt"))
         integ[prec] = path.integrated.cpu().numpy().astype(np.float64)
         log(f"{prec}: {res[prec]['value']:.0f} windows/s, {ms_step:.1f} ms/step, conv "
             f"{res[prec]['conv']['tflops']:.1f} TFLOP/s, stages {res[prec]['stages_ms']}")
