@@ -295,6 +295,49 @@ def inject_leg(args, P, log):
     return res
 
 
+# bytes per stored activation element a conv reads (input), writes (output)
+# and adds (residual), per precision and role: the block's first conv, its
+# second, the 1x1 projection.  bf16f stores a block's inner activation as BF16
+# and the residual stream (block inputs, outputs, projections) as FP32; fp8
+# stores BF16 activations and quantises them on load.
+CONV_ELEM_BYTES = {
+    "f32": {"c1": (4, 4, 0), "c2": (4, 4, 4), "pj": (4, 4, 0)},
+    "bf16": {"c1": (2, 2, 0), "c2": (2, 2, 2), "pj": (2, 2, 0)},
+    "fp8": {"c1": (2, 2, 0), "c2": (2, 2, 2), "pj": (2, 2, 0)},
+    "bf16f": {"c1": (4, 2, 0), "c2": (2, 4, 4), "pj": (4, 4, 0)},
+}
+
+
+def conv_roofline(arch, prec, layer_ms, layer_flops, windows, steps):
+    """Per-layer roofline of the convs: each layer is bounded by the larger of
+    its MFMA time at the precision's dense peak and its HBM time at 8 TB/s for
+    the algorithmic bytes (input rows it reads, output, residual, weights
+    once per 8192-window batch); frac = sum of those bounds / measured time."""
+    wbytes = {"f32": 4, "bf16": 2, "bf16f": 2, "fp8": 1}[prec]
+    l_conv = (arch.window + 2 * (arch.kernel // 2) - arch.kernel) // arch.stem_stride + 1
+    L = (l_conv - 1) // 2 + 1 if arch.stem_pool else l_conv
+    shapes = []
+    for _, c_in, c_out, stride, proj in arch.block_list():
+        lo = (L - 1) // stride + 1
+        shapes.append(("c1", L, lo, c_in, c_out, arch.kernel))
+        if proj:
+            shapes.append(("pj", lo, lo, c_in, c_out, 1))   # reads only the rows it uses
+        shapes.append(("c2", lo, lo, c_out, c_out, arch.kernel))
+        L = lo
+    n_batch = -(-windows // 8192)
+    bound, meas, n_hbm = 0.0, 0.0, 0
+    for (role, l_in, l_out, c_in, c_out, k), ms, fl in zip(shapes, layer_ms, layer_flops):
+        bi, bo, br = CONV_ELEM_BYTES[prec][role]
+        nbytes = windows * (l_in * c_in * bi + l_out * c_out * (bo + br)) + n_batch * c_in * c_out * k * wbytes
+        t_mfma = fl / steps / (PEAK_TFLOPS[prec] * 1e12)
+        t_hbm = nbytes / (PEAK_HBM_GBS * 1e9)
+        n_hbm += t_hbm > t_mfma
+        bound += max(t_mfma, t_hbm)
+        meas += ms / steps * 1e-3
+    return {"bound_ms": 1e3 * bound, "measured_ms": 1e3 * meas, "frac": bound / meas,
+            "hbm_bound_layers": int(n_hbm), "mfma_bound_layers": len(shapes) - int(n_hbm)}
+
+
 def gn_bytes(arch, windows):
     """Algorithmic HBM bytes of the GroupNorm launches over `windows` windows.
     Per conv, the finalize kernel reads the conv's statistics (a sum and a sum
@@ -576,6 +619,8 @@ def main():
                      "launches_per_step": int(prof["launches"][conv].sum() // args.steps),
                      "frac": conv_flop / conv_ms * 1e-9 / PEAK_TFLOPS[prec]},
             "whiten_gbs": wh_bytes / (stage_ms[2] * 1e-3) * 1e-9,
+            "conv_layer_roofline": conv_roofline(arch, prec, prof["ms"][conv], prof["flops"][conv], path.n_windows,
+                                                 args.steps),
             "layers": {"ms": prof["ms"].tolist(), "flops": prof["flops"].tolist(),
                        "launches": prof["launches"].tolist(), "tiles": net.tiles()},
         }
@@ -598,6 +643,7 @@ def main():
         precisions[prec] = {"value": r["value"], "ms_per_step": r["ms_per_step"],
                             "speedup_vs_f32": r["value"] / res[head]["value"], "tau_vs_f32": tau,
                             "conv_tflops": r["conv"]["tflops"], "conv_mfma_frac": r["conv"]["frac"],
+                            "conv_layer_roofline": r["conv_layer_roofline"],
                             "stages_ms": r["stages_ms"]}
     h = res[head]
     n_launch = h["conv"]["launches_per_step"]
