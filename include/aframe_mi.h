@@ -100,8 +100,8 @@ af_status af_psd_estimate(const void* x, af_dtype xt, int64_t n_ch, int64_t n, i
 
 /* ------------------------------------------------------------------------
  * Whitening (Sec. IV.B: PSD -> whitening filter -> whiten in the frequency
- * domain -> crop 0.5 s per edge; Sec. VI; Table III "cropping corruption
- * from whitening filter").  The filter is the inverse ASD with bins below
+ * domain -> crop 0.5 s per edge; Sec. VI; Table III, the row for cropping
+ * the filter's corrupted edges).  The filter is the inverse ASD with bins below
  * `highpass` zeroed, transformed to a zero-phase impulse response and
  * truncated with a Hann taper to |m| < M = fduration*fs/2 taps per side:
  *     y[c][i] = sqrt(2/fs) * sum_m h_j[c][m] * prescale * x[c][out_start + i - m]
