@@ -124,6 +124,16 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
     for (int e = lane; e < 5 * C; e += 64) sbias[e] = a.bias[e];
     auto bias = [&](int l) { return *(const f4v*)(sbias + l * C + 4 * g); };
     auto buf = [&](int b) { return act + b * G::BUF; };
+    // the carried rows: 4 buffers x TAIL rows x UPR 16-byte units, at most two
+    // per lane; their element offsets (front of the buffer) are fixed
+    constexpr int NCARRY = 4 * TAIL * UPR;
+    static_assert(NCARRY <= 128, "two carried units per lane at most");
+    int coff[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int e = lane + 64 * i, b = e / (TAIL * UPR), u = e % (TAIL * UPR);
+        coff[i] = b * G::BUF + (u / UPR) * PITCH + (u % UPR) * 8;
+    }
     const int nsteps = (L + 12 + T - 1) / T;
 
     int64_t win = blockIdx.x;
@@ -146,10 +156,9 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
         };
         // window start: the carried rows lie before the window (zero); the
         // input's carried samples are those of times -3 .. 2
-        for (int e = lane; e < 4 * TAIL * UPR; e += 64) {
-            const int b = e / (TAIL * UPR), u = e % (TAIL * UPR);
-            *(uint4*)(buf(b) + (u / UPR) * PITCH + (u % UPR) * 8) = make_uint4(0u, 0u, 0u, 0u);
-        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+            if (lane + 64 * i < NCARRY) *(uint4*)(act + coff[i]) = make_uint4(0u, 0u, 0u, 0u);
         if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = sample(lane / TAIL, lane % TAIL - 3);
         // samples of times s0 + 3 .. s0 + T + 2 of step 0
         float nx[2];
@@ -256,11 +265,9 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
             wave_lds_sync();
 
             // carry the last TAIL rows of every buffer, and of the input, to the front
-            for (int e = lane; e < 4 * TAIL * UPR; e += 64) {   // whole rows: T keeps the swizzle phase
-                const int b = e / (TAIL * UPR), u = e % (TAIL * UPR);
-                const int off = (u / UPR) * PITCH + (u % UPR) * 8;
-                *(uint4*)(buf(b) + off) = *(const uint4*)(buf(b) + T * PITCH + off);
-            }
+#pragma unroll
+            for (int i = 0; i < 2; ++i)   // whole rows: T keeps the swizzle phase
+                if (lane + 64 * i < NCARRY) *(uint4*)(act + coff[i]) = *(const uint4*)(act + coff[i] + T * PITCH);
             if (lane < 2 * TAIL) xs[(lane / TAIL) * G::XN + lane % TAIL] = xs[(lane / TAIL) * G::XN + T + lane % TAIL];
             wave_lds_sync();
         };
