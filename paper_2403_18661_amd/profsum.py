@@ -19,8 +19,9 @@ Optional ``--sq DIR`` runs (``--pmc`` with SQ_* counters, as many as one
 pass collects) add, per group, each counter summed over the group's
 dispatches and divided by their number.
 
-The summary ends with ``source_sha256`` of the kernel sources, so that a
-reader of the figures can tell whether the kernels changed since.
+The summary ends with the kernel sources its figures depend on
+(``--sources``, default: all of them) and their ``source_sha256``, so that a
+reader of the figures can tell whether those kernels changed since.
 """
 import argparse
 import csv
@@ -29,13 +30,13 @@ import os
 import re
 
 KERNEL_SOURCES = ("csrc/net_kernels.h", "csrc/gn_kernels.h", "csrc/net.hip", "csrc/fused_tiny.h", "csrc/whiten.hip", "csrc/psd.hip",
-                  "csrc/fft_lds.h")
+                  "csrc/fft_lds.h", "csrc/tables.hip", "csrc/common.h")
 
 
-def source_sha256():
+def source_sha256(sources=KERNEL_SOURCES):
     h = hashlib.sha256()
     here = os.path.dirname(os.path.abspath(__file__))
-    for rel in KERNEL_SOURCES:
+    for rel in sources:
         with open(os.path.join(here, rel), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
@@ -73,7 +74,7 @@ def _calib(rows, calib_bytes):
     return calib_bytes / (float(big["Counter_Value"]) * 1024.0), float(big["Counter_Value"])
 
 
-def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=()):
+def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=(), sources=KERNEL_SOURCES):
     calib_bytes = calib_mb * 2 ** 20
     kt = _rows(trace, "kernel_trace.csv")
     ks = _rows(trace, "kernel_stats.csv")
@@ -115,7 +116,8 @@ def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=()):
         lines.append(f"  {float(r['Percentage']):6.2f}%  calls {int(r['Calls']):5d}  avg "
                      f"{float(r['AverageNs']) * 1e-6:8.4f} ms  {r['Name'][:110]}")
     lines.append("")
-    lines.append(f"source_sha256 {source_sha256()}")
+    lines.append("source_files " + " ".join(sources))
+    lines.append(f"source_sha256 {source_sha256(sources)}")
     return "\n".join(lines) + "\n"
 
 
@@ -128,7 +130,9 @@ def read_traffic(path):
     except OSError:
         return {}
     m = re.search(r"^source_sha256 (\w+)", text, re.M)
-    if not m or m.group(1) != source_sha256():
+    f = re.search(r"^source_files (.+)$", text, re.M)
+    sources = tuple(f.group(1).split()) if f else KERNEL_SOURCES
+    if not m or not set(sources) <= set(KERNEL_SOURCES) or m.group(1) != source_sha256(sources):
         return {}
     out = {}
     block = text.split("groups (", 1)[1].split("\n\n", 1)[0].splitlines()[2:]
@@ -148,8 +152,14 @@ def main():
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--sq", action="append", default=[], help="directory of a --pmc run of SQ counters")
+    ap.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
+                    help="kernel sources (relative to the package) the profiled kernels are built from")
     a = ap.parse_args()
-    text = summarise(a.trace, a.fetch, a.write, a.calib_mb, _groups(a.group), a.cmd, sq_dirs=a.sq)
+    unknown = set(a.sources) - set(KERNEL_SOURCES)
+    if unknown:
+        ap.error(f"not kernel sources: {sorted(unknown)}")
+    text = summarise(a.trace, a.fetch, a.write, a.calib_mb, _groups(a.group), a.cmd, sq_dirs=a.sq,
+                     sources=tuple(a.sources))
     with open(a.out, "w") as f:
         f.write(text)
     print(text)
