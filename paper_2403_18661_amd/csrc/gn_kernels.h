@@ -16,13 +16,14 @@ namespace afm {
 // The GroupNorm net's stem for any width C dividing 256: conv, GroupNorm,
 // ReLU and (with a.pool) max-pool k3 s2 p1, one window per workgroup of 256
 // threads, writing only the stem's output.  The conv (NCH x KW taps per
-// output) is cheap, so it is computed twice instead of being stored: pass 1
-// accumulates per-channel sums and sums of squares in FP64 (thread t takes
-// channel t % C and rows t / C, t / C + 256 / C, ...), reduced across the
-// threads of a channel, then per group in channel order; pass 2 recomputes
-// each conv value where the output needs it, normalises it and applies ReLU
-// (and the pool: every candidate is >= 0, so 0 starts the max).  Samples are
-// staged in LDS; weights in registers.
+// output) is cheap, so it is computed twice instead of being stored.  Thread
+// t takes channel t % C and the (t / C)-th of 256 / C consecutive row blocks.
+// Pass 1 accumulates per-channel sums and sums of squares (FP32 over 16 rows,
+// then FP64), reduced across the threads of a channel in block order, then
+// per group in channel order; pass 2 recomputes each conv value where the
+// output needs it, normalises it and applies ReLU, and the pool takes the
+// maximum of rows 2p - 1 .. 2p + 1 (its last row is the next output's first,
+// so it is computed once).  Samples are staged in LDS; weights in registers.
 template <int NCH, int KW>
 __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a, const float* gamma, const float* beta, int G) {
     extern __shared__ float xs[];  // [n_ch][window]
@@ -52,11 +53,19 @@ __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a, const float* g
             }
         return acc;
     };
+    const int rb = tid / C;
+    const int nrow = (a.L_conv + rstep - 1) / rstep, r_lo = rb * nrow, r_hi = min(a.L_conv, r_lo + nrow);
     double s = 0.0, q = 0.0;
-    for (int t = tid / C; t < a.L_conv; t += rstep) {
-        const double v = conv(t);
-        s += v;
-        q += v * v;
+    for (int t0 = r_lo; t0 < r_hi; t0 += 16) {
+        float fs = 0.f, fq = 0.f;
+        const int t1 = min(t0 + 16, r_hi);
+        for (int t = t0; t < t1; ++t) {
+            const float v = conv(t);
+            fs += v;
+            fq = fmaf(v, v, fq);
+        }
+        s += (double)fs;
+        q += (double)fq;
     }
     part[0][tid] = s;
     part[1][tid] = q;
@@ -89,15 +98,19 @@ __global__ void __launch_bounds__(256) gn_stem_kernel(StemArgs a, const float* g
     __syncthreads();
     const float S = sc[c], H = sh[c];
     float* out = (float*)a.out + (size_t)b * a.L_out * C;
-    for (int p = tid / C; p < a.L_out; p += rstep) {
-        float m = 0.f;
-        if (a.pool) {
-            for (int r = 2 * p - 1; r <= 2 * p + 1; ++r)
-                if (r >= 0 && r < a.L_conv) m = fmaxf(m, fmaf(conv(r), S, H));
-        } else {
-            m = fmaxf(fmaf(conv(p), S, H), 0.f);
+    const int nout = (a.L_out + rstep - 1) / rstep, p_lo = rb * nout, p_hi = min(a.L_out, p_lo + nout);
+    // ReLU of the normalised conv row r; rows outside the conv are 0 (every
+    // pool candidate is >= 0)
+    auto act = [&](int r) { return (r >= 0 && r < a.L_conv) ? fmaxf(fmaf(conv(r), S, H), 0.f) : 0.f; };
+    if (a.pool) {
+        float prev = p_lo < p_hi ? act(2 * p_lo - 1) : 0.f;
+        for (int p = p_lo; p < p_hi; ++p) {
+            const float r0 = act(2 * p), r1 = act(2 * p + 1);
+            out[(size_t)p * C + c] = fmaxf(fmaxf(prev, r0), r1);
+            prev = r1;
         }
-        out[(size_t)p * C + c] = m;
+    } else {
+        for (int p = p_lo; p < p_hi; ++p) out[(size_t)p * C + c] = act(p);
     }
 }
 
@@ -218,10 +231,24 @@ __global__ void __launch_bounds__(256) gn_finalize_kernel(const float* stats, in
     const float* st = stats + b * nblk * 2 * C;
     for (int idx = tid; idx < per * C; idx += 256) {
         const int c = idx % C, pp = idx / C;
+        // 8 blocks' values loaded before they are added (in block order; a
+        // block past the end reads a valid one and adds an exact zero)
+        constexpr int U = 8;
         double s = 0.0, q = 0.0;
-        for (int k = pp; k < nblk; k += per) {
-            s += (double)st[(size_t)k * 2 * C + c];
-            q += (double)st[(size_t)k * 2 * C + C + c];
+        for (int k0 = pp; k0 < nblk; k0 += U * per) {
+            float vs[U], vq[U];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const int k = k0 + u * per < nblk ? k0 + u * per : pp;
+                vs[u] = st[(size_t)k * 2 * C + c];
+                vq[u] = st[(size_t)k * 2 * C + C + c];
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const bool ok = k0 + u * per < nblk;
+                s += ok ? (double)vs[u] : 0.0;
+                q += ok ? (double)vq[u] : 0.0;
+            }
         }
         part[0][idx] = s;
         part[1][idx] = q;
