@@ -78,6 +78,8 @@ def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=(), so
     calib_bytes = calib_mb * 2 ** 20
     kt = _rows(trace, "kernel_trace.csv")
     ks = _rows(trace, "kernel_stats.csv")
+    if not ks:
+        raise ValueError(f"{trace}: kernel_stats.csv holds no rows (profiler output not yet complete)")
     fr = _rows(fetch, "counter_collection.csv")
     wr = _rows(write, "counter_collection.csv")
     kf, f_raw = _calib(fr, calib_bytes)
