@@ -183,6 +183,12 @@ def timeslide_leg(args, P, log):
     pmc = read_traffic(os.path.join(os.path.dirname(os.path.abspath(__file__)), "profiles", "timeslide_kernel.txt"))
     res["traffic_bytes_per_launch"] = pmc.get("timeslide", {}).get("traffic")
     res["input_bytes_per_launch"] = 4 * 2 * TINY_ARCH.window * plan.n_windows
+    # the stem's products run on the FP32 matrix cores (the BF16 mode keeps the
+    # stem in FP32), the rest on BF16: the kernel's own MFMA time bound
+    stem_flop = 2.0 * TINY_ARCH.window * TINY_ARCH.in_ch * TINY_ARCH.stem_ch * TINY_ARCH.kernel * plan.n_windows
+    bound_ms = 1e3 * (stem_flop / (PEAK_TFLOPS["f32"] * 1e12) + (flop - stem_flop) / (PEAK_TFLOPS["bf16"] * 1e12))
+    res["mixed_mfma_bound_ms"] = bound_ms
+    res["frac_of_mixed_mfma_bound"] = bound_ms / ms
     log(f"timeslide: {res['value']:.0f} windows/s, {res['achieved_tflops']:.1f} TFLOP/s")
     res["events"] = events_leg(P, plan, seg_len, len(shifts), net.window, fs, log)
     del plan, y

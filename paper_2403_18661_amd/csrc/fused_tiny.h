@@ -53,10 +53,17 @@ struct FusedTinyArgs {
     unsigned int* next;        // window queue counter (zero at launch)
 };
 
-// Waits for this wavefront's outstanding LDS operations and keeps the
-// compiler from moving memory accesses across the point; global loads in
-// flight are not waited for.
-__device__ __forceinline__ void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+// Orders this wavefront's LDS accesses across the point: stores before it
+// are seen by loads after it in every lane of the wavefront.  A wavefront's
+// LDS operations execute in issue order, so this needs no wait in the
+// instruction stream: wavefront-scope release and acquire fences around a
+// wave barrier keep the compiler from moving accesses across it.  Global
+// loads in flight are not waited for.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
 
 // BF16 pair: round to nearest even, then ReLU on the bit patterns (one packed
 // signed 16-bit max).
