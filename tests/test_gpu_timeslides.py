@@ -49,6 +49,18 @@ def test_zero_shift_equals_plain_windows():
     np.testing.assert_array_equal(ts[nw:], plain)     # a full-length shift is no shift
 
 
+def test_segments_shorter_than_a_window_give_no_windows():
+    # every segment shorter than a window: no windows, an empty result and no
+    # launch, in both the layer and the whole-network path
+    P = need_gpu()
+    y = dev(np.zeros((2, 6000), np.float32))
+    assert P.timeslide_n_windows([3071, 2000], 2, 3072, 2048) == 0
+    for prec in ("f32", "bf16"):
+        net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=1), prec)
+        out = P.score_timeslides(net, y, [0, 3500], [3071, 2000], [2048, 4096])
+        assert out.numel() == 0
+
+
 def test_rejects_segment_outside_series():
     P = need_gpu()
     net = P.Net(TINY_ARCH, make_params(TINY_ARCH, seed=1), "f32")
