@@ -518,6 +518,11 @@ def main():
     ap.add_argument("--no-rates", action="store_true")
     ap.add_argument("--no-inject", action="store_true")
     ap.add_argument("--no-gn", action="store_true")
+    ap.add_argument("--save-tiles", default=None,
+                    help="write each precision's chosen conv tile candidates (JSON) after autotuning")
+    ap.add_argument("--load-tiles", default=None,
+                    help="use the conv tile candidates of a --save-tiles file instead of autotuning "
+                         "(profiler passes that must run the same kernels)")
     ap.add_argument("--no-whiten24", action="store_true")
     ap.add_argument("--whiten-only", action="store_true",
                     help="run only the 24 h whitening leg (e.g. to profile its kernel) and print its JSON")
@@ -573,6 +578,11 @@ def main():
         return
     res = {}
     integ = {}
+    tiles_in = None
+    if args.load_tiles:
+        with open(args.load_tiles) as f:
+            tiles_in = json.load(f)
+    tiles_out = {}
     for prec in args.precisions.split(","):
         net = P.Net(arch, params, prec)
         if prec == "fp8":
@@ -581,9 +591,14 @@ def main():
             c = np.random.default_rng(99).standard_normal((2, 3072 + 1000 * 63)).astype(np.float32)
             net.calibrate(torch.from_numpy(c).cuda(), 1000)
         path = OfflinePath(net, x.shape[1], cfg, batch=args.batch)
-        if not args.no_autotune:
+        if tiles_in is not None:
+            for layer, chosen in enumerate(tiles_in[prec], start=1):
+                net.set_tile(layer, chosen)
+            log(f"{prec}: conv tiles from {args.load_tiles}")
+        elif not args.no_autotune:
             changed = net.autotune(batch=min(args.batch, 2048), ws=path.ws_net)
             log(f"{prec}: autotune switched {changed} of {net.n_layers - 2} conv layers")
+        tiles_out[prec] = [t[3] for t in net.tiles()]
         for _ in range(args.warmup):
             path.run(xd)
         torch.cuda.synchronize()
@@ -639,6 +654,9 @@ def main():
     if args.layers_out:
         with open(args.layers_out, "w") as f:
             json.dump({p: r["layers"] for p, r in res.items()}, f)
+    if args.save_tiles:
+        with open(args.save_tiles, "w") as f:
+            json.dump(tiles_out, f)
     import scipy.stats
     head = "f32" if "f32" in res else list(res)[0]
     precisions = {}

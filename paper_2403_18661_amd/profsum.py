@@ -15,6 +15,14 @@ whose warm-up and autotuning dispatches come first) are averaged.
     python -m paper_2403_18661_amd.profsum --trace DIR --fetch DIR --write DIR \\
         --calib-mb 1024 --group 'f32=conv_mfma_kernel<afm::PF32,@280' --cmd '...' --out FILE
 
+A launch sequence is named as ``label=regex@start:count``: the ``count``
+consecutive dispatches matching ``regex`` from position ``start`` (negative:
+from the end) of the matches, one row each; e.g. the 35 conv launches of one
+8192-window batch, layer by layer.  The counter runs are separate processes,
+so their dispatches are matched to the trace's by position; a row whose
+kernel differs between the runs (an autotuner that chose another tile) is
+marked.
+
 Optional ``--sq DIR`` runs (``--pmc`` with SQ_* counters, as many as one
 pass collects) add, per group, each counter summed over the group's
 dispatches and divided by their number.
@@ -50,6 +58,32 @@ def _rows(d, suffix):
         return list(csv.DictReader(f))
 
 
+def _seqs(specs):
+    out = []
+    for s in specs:
+        label, rest = s.split("=", 1)
+        rx, rng = rest.rsplit("@", 1)
+        start, count = (int(v) for v in rng.split(":"))
+        if count < 1:
+            raise ValueError(f"{s}: count must be positive")
+        out.append((label, re.compile(rx), start, count))
+    return out
+
+
+def _slice(rows, rx, start, count):
+    sel = [r for r in rows if rx.search(r["Kernel_Name"])]
+    end = start + count
+    got = sel[start:end if end != 0 else None]
+    if len(got) != count:
+        raise ValueError(f"{rx.pattern}: {len(sel)} dispatches, no {count} from position {start}")
+    return got
+
+
+def _short(name):
+    m = re.search(r"<(.*)>\(", name)
+    return re.sub(r"afm::|\s", "", m.group(1)) if m else name[:60]
+
+
 def _groups(specs):
     out = []
     for s in specs:
@@ -74,7 +108,7 @@ def _calib(rows, calib_bytes):
     return calib_bytes / (float(big["Counter_Value"]) * 1024.0), float(big["Counter_Value"])
 
 
-def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=(), sources=KERNEL_SOURCES):
+def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=(), sources=KERNEL_SOURCES, seqs=()):
     calib_bytes = calib_mb * 2 ** 20
     kt = _rows(trace, "kernel_trace.csv")
     ks = _rows(trace, "kernel_stats.csv")
@@ -111,6 +145,19 @@ def summarise(trace, fetch, write, calib_mb, groups, cmd, top=12, sq_dirs=(), so
                     agg[r["Counter_Name"]] = agg.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
             vals = "  ".join(f"{k} {v / len(ids):.4g}" for k, v in sorted(agg.items()))
             lines.append(f"  {label:10s} {vals}")
+    for label, rx, start, count in seqs:
+        t, f, w = (_slice(rows, rx, start, count) for rows in (kt, fr, wr))
+        lines.append("")
+        lines.append(f"launch sequence {label} ({count} dispatches matching {rx.pattern} from position {start}; "
+                     "bytes as above; * = another kernel in a counter run):")
+        lines.append(f"  {'#':>3s} {'ms':>8s} {'fetch_MB':>9s} {'write_MB':>9s} {'GB/s':>7s}  kernel")
+        for i, (rt, rf, rw) in enumerate(zip(t, f, w)):
+            dur = (int(rt["End_Timestamp"]) - int(rt["Start_Timestamp"])) * 1e-6
+            fb = float(rf["Counter_Value"]) * 1024 * kf
+            wb = float(rw["Counter_Value"]) * 1024 * kw
+            mark = "" if rt["Kernel_Name"] == rf["Kernel_Name"] == rw["Kernel_Name"] else " *"
+            lines.append(f"  {i + 1:3d} {dur:8.4f} {fb / 1e6:9.2f} {wb / 1e6:9.2f} {(fb + wb) / dur * 1e-6:7.0f}  "
+                         f"{_short(rt['Kernel_Name'])}{mark}")
     lines.append("")
     lines.append(f"--stats, top {top} kernels by total time (all dispatches of the run, incl. autotuning):")
     ks = sorted(ks, key=lambda r: -float(r["TotalDurationNs"]))[:top]
@@ -154,6 +201,7 @@ def main():
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--out", required=True)
     ap.add_argument("--sq", action="append", default=[], help="directory of a --pmc run of SQ counters")
+    ap.add_argument("--seq", action="append", default=[], help="label=regex@start:count, one row per dispatch")
     ap.add_argument("--sources", nargs="+", default=list(KERNEL_SOURCES),
                     help="kernel sources (relative to the package) the profiled kernels are built from")
     a = ap.parse_args()
@@ -161,7 +209,7 @@ def main():
     if unknown:
         ap.error(f"not kernel sources: {sorted(unknown)}")
     text = summarise(a.trace, a.fetch, a.write, a.calib_mb, _groups(a.group), a.cmd, sq_dirs=a.sq,
-                     sources=tuple(a.sources))
+                     sources=tuple(a.sources), seqs=_seqs(a.seq))
     with open(a.out, "w") as f:
         f.write(text)
     print(text)

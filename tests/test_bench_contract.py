@@ -1,9 +1,11 @@
-"""bench.py's command-line contract on a host without a GPU: more than one
+"""bench.py's command-line contract on a host without a GPU (more than one
 GPU is refused with a message and a non-zero status, before anything touches
-a device."""
+a device), and the reading of the profile summaries it cites."""
 import os
 import subprocess
 import sys
+
+import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -33,3 +35,19 @@ def test_profile_traffic_is_dropped_when_its_sources_change(tmp_path):
     foreign = tmp_path / "foreign.txt"   # a file that is not a kernel source is never trusted
     foreign.write_text(body + "source_files bench.py\nsource_sha256 " + profsum.source_sha256(srcs) + "\n")
     assert profsum.read_traffic(str(foreign)) == {}
+
+
+def test_profile_launch_sequences():
+    # label=regex@start:count picks count consecutive matches from start
+    # (negative: from the end), and refuses a range the run does not hold
+    from paper_2403_18661_amd import profsum
+    (label, rx, start, count), = profsum._seqs(["bf16_layers=conv<P,@-4:2"])
+    assert (label, start, count) == ("bf16_layers", -4, 2)
+    rows = [{"Kernel_Name": n} for n in ("conv<P,a>", "stem", "conv<P,b>", "conv<P,c>", "conv<P,d>", "conv<Q,e>")]
+    assert [r["Kernel_Name"] for r in profsum._slice(rows, rx, start, count)] == ["conv<P,a>", "conv<P,b>"]
+    assert [r["Kernel_Name"] for r in profsum._slice(rows, rx, -2, 2)] == ["conv<P,c>", "conv<P,d>"]
+    with pytest.raises(ValueError):
+        profsum._slice(rows, rx, -5, 2)
+    with pytest.raises(ValueError):
+        profsum._seqs(["x=y@0:0"])
+    assert profsum._short("void afm::conv_mfma_kernel<afm::PBF16, 7, 1>(afm::ConvArgs)") == "PBF16,7,1"
