@@ -207,10 +207,15 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
 #pragma unroll
                     for (int m = 0; m < NT; ++m) xv[s][m] = xb[s][16 * m];
                 __builtin_amdgcn_sched_barrier(0);
+                // raised issue priority while the products run: a wavefront
+                // with MFMAs ready goes before the others' LDS and VALU work
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int s = 0; s < 4; ++s)
 #pragma unroll
                     for (int m = 0; m < NT; ++m) acc[m] = __builtin_amdgcn_mfma_f32_16x16x4f32(ws[s], xv[s][m], acc[m], 0, 0, 0);
+                __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(0);
                 // row TAIL + 16m + r16 keeps the swizzle phase of TAIL + r16
                 const int so = act_off<PITCH, SWZ>(TAIL + r16, g >> 1) + 4 * (g & 1);
 #pragma unroll
@@ -249,6 +254,7 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
 #pragma unroll
                     for (int m = 0; m < NT; ++m) xv[s][m] = *(const bf16x8*)(bsrc[s] + 16 * m * PITCH);
                 __builtin_amdgcn_sched_barrier(0);
+                __builtin_amdgcn_s_setprio(1);
 #pragma unroll
                 for (int s = 0; s < 4; ++s) {
 #pragma unroll
@@ -261,6 +267,7 @@ __global__ void __launch_bounds__(64, 3) fused_tiny_bf16_kernel(FusedTinyArgs a)
                     }
                     __builtin_amdgcn_sched_barrier(0);
                 }
+                __builtin_amdgcn_s_setprio(0);
                 const int tl = s0 - 3 * (l + 1);   // time of output row 0
                 const int so = act_off<PITCH, SWZ>(TAIL + r16, g >> 1) + 4 * (g & 1);
 #pragma unroll
